@@ -1,0 +1,174 @@
+"""Benchmark: site-update attempts/s of the octahedron model with DTr on one MI355X.
+
+Default workload: one L = 2^17 lattice (2^34 sites, 4 GiB bit-packed) from the
+flat zig-zag surface, DTrDB (device-level DTr, block-level single-hit dead
+border with delayed borders), 256 x 256-site device domains, TC=1,1 (8 x 8-site
+thread cells), p = 0.95, q = 0.05.  One step = one MCS (2^34 update attempts:
+4 device-step launches) + the exact W^2 measurement + the height
+autocorrelation C_h(t, s) against a snapshot taken after warm-up.
+
+Prints ONE JSON line.  `value` is attempts/s over the timed steps (inputs
+resident in HBM); `roofline` reports the device-step kernel, timed with HIP
+events on the stream it runs on; `cpu_baseline` times the CPU oracle (the DTr
+emulation) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# VALU issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (32-bit integer lane ops)
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# algorithmic integer lane-ops per update attempt of the method (derivation in the design doc)
+OPS_PER_ATTEMPT = {"DB_accept": 40.0, "DT_noaccept": 28.0}
+
+WORKLOADS = {
+    # name: (L, D, C, scheme, p, q, label)
+    "L131072": (1 << 17, 256, 8, 1, 0.95, 0.05,
+                "octahedron L=131072 (4 GiB packed), DTrDB, D=256x256, TC=1,1, p=0.95 q=0.05"),
+    "L4096": (4096, 256, 8, 0, 1.0, 0.0,
+              "octahedron L=4096 (4 MiB packed), DTrDT, D=256x256, TC=1,1, p=1 q=0"),
+    "L64": (64, 16, 8, 0, 1.0, 0.0, "octahedron L=64, DTrDT, D=16x16, TC=1,1, p=1 q=0"),
+}
+SCHEME_NAME = {0: "DTrDT", 1: "DTrDB", 2: "DTrDTr"}
+
+
+def cpu_baseline(L, D, C, scheme, p, q, budget_s=15.0):
+    """Time the oracle's DTr emulation on a window of 8 x 8 tiles of the same
+    lattice (same global tile ids and random streams): MCS m = 0, 1, 2, ...,
+    each applied to the flat window, counting the attempts of the domains that
+    lie wholly inside it, until about budget_s seconds of CPU work."""
+    import oracle
+
+    tiles = 8
+    W = min(L, tiles * 2 * D)
+    window = (0, 0, W, W)
+    emu = oracle.Emu(L=L, Dx=D, Dy=D, Cx=C, Cy=C, scheme=scheme, p=p, q=q, seed=1, stream=0)
+    attempts, m, el = 0, 0, 0.0
+    while el < budget_s and m < 64:
+        s, valid = oracle.init_flat_window(L, window)
+        t0 = time.perf_counter()
+        if L == W:
+            attempts += emu.mcs(s, m)
+        else:
+            attempts += emu.mcs_window(s, valid, window, m)
+        el += time.perf_counter() - t0
+        m += 1
+    return {"value": attempts / el, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+            "sample": "DTr emulation (single thread) of MCS 0..%d, each on the flat %dx%d-site "
+                      "window (%d x %d tiles) of the L=%d lattice; %d attempts in %.1f s"
+                      % (m - 1, W, W, W // (2 * D), W // (2 * D), L, attempts, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="L131072", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the method's lattice lives on one "
+              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: one process only", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1705_01022_amd as okpz
+
+    L, D, C, scheme, p, q, label = WORKLOADS[args.workload]
+    print("bench: workload %s, warmup %d, steps %d" % (args.workload, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    lat = okpz.Lattice(L, D, D, C, C, scheme, seed=1, stream=0)
+    lat.run(args.warmup, p, q)
+    lat.snapshot()
+    lat.sync()
+    print("bench: warm-up done", file=sys.stderr, flush=True)
+
+    lat.timing(True)
+    lat.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lat.run(1, p, q)
+        mo = lat.measure()
+        ac = lat.autocorr()
+    lat.sync()
+    elapsed = time.perf_counter() - t0
+    tm = lat.get_timing()
+    lat.timing(False)
+    print("bench: timed %d steps in %.3f s (W^2=%.6f, C_h=%.6f)" % (args.steps, elapsed, mo["w2"],
+                                                                   ac["c_h"]),
+          file=sys.stderr, flush=True)
+
+    sites = L * L
+    attempts = args.steps * sites
+    value = attempts / elapsed
+    step_avg_s = tm["step_ms"] / tm["step_launches"] / 1e3
+    # one device step moves the active quarter of the lattice in and out once:
+    # algorithmic bytes = 2 * (L^2/4 sites * 2 bits / 8) = L^2 / 8
+    bytes_per_launch = sites / 8
+    attempts_per_launch = sites / 4
+    accept = not (p in (0.0, 1.0) and q in (0.0, 1.0))
+    ops = OPS_PER_ATTEMPT["DB_accept" if accept else "DT_noaccept"]
+    alu_achieved = attempts_per_launch * ops / step_avg_s / 1e9
+    hbm_achieved = bytes_per_launch / step_avg_s / 1e9
+    line = {
+        "metric": "site-update attempts/s",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": label,
+            "L": L, "dom": [D, D], "cell": [C, C], "scheme": SCHEME_NAME[scheme], "p": p, "q": q,
+            "step": "1 MCS (L^2 attempts, 4 device-step launches) + exact W^2 + C_h(t,s)",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "step_kernel<%s>" % SCHEME_NAME[scheme],
+            "bound": "alu",
+            "achieved": alu_achieved,
+            "peak": VALU_PEAK_GOPS,
+            "unit": "Gop/s",
+            "frac": alu_achieved / VALU_PEAK_GOPS,
+            "traffic": None,
+            "ops_per_attempt": ops,
+            "avg_launch_ms": step_avg_s * 1e3,
+            "launches": tm["step_launches"],
+            "hbm_achieved_GBs": hbm_achieved,
+            "hbm_peak_GBs": HBM_PEAK_GBS,
+            "hbm_frac": hbm_achieved / HBM_PEAK_GBS,
+        },
+        "kernel_attempts_per_s": attempts_per_launch / step_avg_s,
+        "measure_ms_per_step": tm["measure_ms"] / max(1, args.steps),
+        "paper_context": {"value": 9e9, "unit": "attempts/s",
+                          "hardware": "Kepler GTX Titan Black / Tesla K80, DTrDB, L=2^16"},
+    }
+    lat.close()
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline (about %.0f s)" % args.cpu_budget, file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(L, D, C, scheme, p, q, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,256 @@
+/*
+ * okpz.h - C ABI of the MI355X (gfx950) octahedron-model KPZ simulator.
+ *
+ * The library runs random-sequential (RS) updates of the 2+1-dimensional
+ * octahedron model (Kelling, Odor, Gemming, arXiv:1705.01022, Sec. 2.1) on a
+ * GPU-resident, bit-packed slope lattice, parallelised by double tiling with
+ * a random origin every Monte Carlo step (DTr, Sec. 3) across workgroups and
+ * single-hit DT, DB (delayed borders) or DTr updates of thread cells inside
+ * each workgroup (Sec. 3.1).  It also measures the roughness W^2 (Sec. 2.1)
+ * and the height autocorrelation C_h(t,s) (Sec. 2.1) with exact integer
+ * reductions.
+ *
+ * Conventions
+ *   - Sites (x, y) in [0, L)^2, periodic, x fast.  Slope bits per site:
+ *     sx = 1 iff h(x,y) - h(x-1,y) = +1, sy = 1 iff h(x,y) - h(x,y-1) = +1
+ *     (one slope per direction is stored on the site, Sec. 3, DB scheme).
+ *   - Host site arrays ("sites") are L*L bytes, index y*L + x,
+ *     bit 0 = sx, bit 1 = sy, other bits zero.
+ *   - Packed device layout ("words"): uint32 word (y/4)*(L/4) + x/4 holds the
+ *     4x4 sites of its block (the paper's bit-coded lattice, Sec. 3.1):
+ *     bit 4*(y%4) + x%4 is sx, bit 16 + 4*(y%4) + x%4 is sy.  L*L/4 bytes.
+ *   - One MCS is L*L update attempts (Sec. 2.1, time unit).
+ *   - Heights use the gauge h(0,0) = 0; every reported observable is
+ *     invariant under the gauge.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by
+ *     (seed, stream), counters built from (MCS, step, tile, cell, round), so
+ *     results depend only on the parameters and the sequence of run calls:
+ *     never on launch shape, batch composition or stream.
+ *
+ * Errors: every call returns OKPZ_OK (0) or a negative status; on OKPZ_EHIP
+ * okpz_last_error() holds the HIP error text of the calling thread.  A
+ * failed call leaves the lattice unchanged unless it says otherwise.
+ *
+ * Threading: one handle must not be used by two threads at once; different
+ * handles are independent.  All work of a handle runs on its HIP stream, in
+ * order; calls that return host data synchronise that stream.
+ *
+ * Ownership: the library owns every device buffer it allocates and frees it
+ * in okpz_destroy.  Buffers passed by the caller stay the caller's.
+ */
+#ifndef OKPZ_H
+#define OKPZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define OKPZ_OK 0
+#define OKPZ_EINVAL (-1)    /* invalid argument or parameter combination     */
+#define OKPZ_ENOMEM (-2)    /* device or host allocation failed               */
+#define OKPZ_EHIP (-3)      /* HIP runtime error, see okpz_last_error()        */
+#define OKPZ_EOVERFLOW (-4) /* a counter or an exact reduction would overflow  */
+#define OKPZ_ESTATE (-5)    /* call not valid in the current state             */
+
+/* block-level (thread-cell) decomposition schemes, Sec. 3.1 */
+#define OKPZ_BLOCK_DT 0  /* single-hit double tiling: random quadrant per round  */
+#define OKPZ_BLOCK_DB 1  /* single-hit dead border, delayed borders, random cell origin per round */
+#define OKPZ_BLOCK_DTR 2 /* single-hit DT with the cell origin re-drawn per round */
+
+/* device-level origin of the double tiling */
+#define OKPZ_ORIGIN_RANDOM 0 /* DTr: uniform over all sites every MCS (Sec. 3, DTr)     */
+#define OKPZ_ORIGIN_FIXED 1  /* plain DT: origin stays at (0,0) (negative control)      */
+#define OKPZ_ORIGIN_COARSE 2 /* origin on the 4x4-site word grid (cDB-like control)     */
+
+/*
+ * Simulation parameters.  Physics parameters (Sec. 3.1 notation DTrDT etc.
+ * and TC=log2(cell_x/4),log2(cell_y/4)):
+ *   L             lateral size, power of two, 16 <= L <= 2^17
+ *   dom_x, dom_y  device domain (sub-tile) size in sites; tiles are
+ *                 2*dom_x x 2*dom_y.  Powers of two, >= 4, 2*dom <= L,
+ *                 (dom_x/4 + 1)*(dom_y/4 + 1)*4 bytes <= 64 KiB of LDS.
+ *   cell_x,cell_y thread-cell size in sites, powers of two, 2 .. 64,
+ *                 cell <= dom, at most 4096 cells per domain.
+ *                 (TC=1,1 is 8 x 8 sites.)
+ *   block_scheme  OKPZ_BLOCK_DT / _DB / _DTR
+ *   seed, stream  Philox key; one stream per independent realization
+ *   origin_mode   OKPZ_ORIGIN_RANDOM (the method) or a negative control
+ */
+typedef struct okpz_params {
+    uint32_t L;
+    uint32_t dom_x, dom_y;
+    uint32_t cell_x, cell_y;
+    int32_t block_scheme;
+    uint32_t seed;
+    uint32_t stream;
+    int32_t origin_mode;
+    uint32_t reserved; /* must be 0 */
+} okpz_params;
+
+/* 128-bit two's-complement integer: value = hi * 2^64 + lo */
+typedef struct okpz_i128 {
+    uint64_t lo;
+    int64_t hi;
+} okpz_i128;
+
+/*
+ * Exact height moments split by sublattice parity ((x+y) even / odd):
+ * n = number of sites, s1 = sum of h, s2 = sum of h^2 (gauge h(0,0) = 0).
+ *   w2     = (N*S2 - S1^2) / N^2 with N = L^2, S = even + odd: the roughness
+ *            of Sec. 2.1 taken literally (1/4 on the flat zig-zag surface).
+ *   w2_sub = mean of the two within-parity variances (0 on every flat
+ *            surface; 0 <= w2 - w2_sub <= 1/4).
+ * Both doubles are the exact rational values rounded once to nearest.
+ */
+typedef struct okpz_moments {
+    uint64_t mcs;
+    int64_t n_even, n_odd;
+    okpz_i128 s1_even, s1_odd, s2_even, s2_odd;
+    double w2, w2_sub;
+} okpz_moments;
+
+/*
+ * Height autocorrelation between the current state (time t) and the
+ * snapshot (time s): C_h(t,s) = <h_t h_s> - <h_t><h_s> over sites (Sec. 2.1;
+ * C_h(s,s) = W^2(s)).  s_ts = sum h_t h_s, s1_t = sum h_t, s1_s = sum h_s;
+ * c_h = (N s_ts - s1_t s1_s) / N^2 rounded once to nearest.
+ */
+typedef struct okpz_correlation {
+    uint64_t t, s;
+    okpz_i128 s_ts, s1_t, s1_s;
+    double c_h;
+} okpz_correlation;
+
+typedef struct okpz_lattice okpz_lattice;
+
+/* Status text for a code (static string, never NULL). */
+const char *okpz_strerror(int status);
+
+/* Last HIP error text of the calling thread ("" if none). */
+const char *okpz_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int okpz_version(void);
+
+/*
+ * Check parameters without allocating anything.  Returns OKPZ_OK or
+ * OKPZ_EINVAL.  Writes the packed lattice size in bytes to *nbytes if
+ * nbytes is not NULL.
+ */
+int okpz_validate(const okpz_params *params, size_t *nbytes);
+
+/*
+ * Create a lattice in the flat zig-zag state h = (x+y) mod 2 at MCS 0 on
+ * the HIP stream `hip_stream` (a hipStream_t; NULL = the default stream).
+ * Allocates the packed lattice (L*L/4 bytes) and small measurement buffers
+ * (about 28*L bytes) on the current device.  *out receives the handle.
+ */
+int okpz_create(const okpz_params *params, void *hip_stream, okpz_lattice **out);
+
+/*
+ * As okpz_create, but the packed lattice lives in caller-owned device memory
+ * `dev_words` of `nbytes` >= L*L/4 bytes (e.g. a torch tensor), 256-byte
+ * aligned.  The caller keeps it alive until okpz_destroy.  The contents are
+ * overwritten with the flat state.
+ */
+int okpz_create_external(const okpz_params *params, void *hip_stream, void *dev_words,
+                         size_t nbytes, okpz_lattice **out);
+
+/* Free the handle and every buffer the library allocated for it. */
+int okpz_destroy(okpz_lattice *lat);
+
+/* Reset to the flat zig-zag state at MCS 0; drops any snapshot. */
+int okpz_init_flat(okpz_lattice *lat);
+
+/*
+ * Load a state from host `sites` (L*L bytes, see Conventions) and set the
+ * MCS counter to `mcs` (< 2^30).  Rejects (OKPZ_EINVAL, lattice unchanged)
+ * any array with bits other than 0-1 set or that is not a valid periodic
+ * surface: every row needs L/2 set sx bits, every column L/2 set sy bits,
+ * and sx[x,y-1] + sy[x,y] = sy[x-1,y] + sx[x,y] on every plaquette.
+ * Drops any snapshot.  Synchronous.
+ */
+int okpz_init_from_host(okpz_lattice *lat, const uint8_t *sites, uint64_t mcs);
+
+/*
+ * Advance n_mcs Monte Carlo steps at deposition probability p and removal
+ * probability q (0 <= p, q <= 1; Sec. 2.1 rule).  Each MCS draws a fresh
+ * random tiling origin and an order of the four domain sets and sweeps them
+ * (Sec. 3, DTr).  Asynchronous on the handle's stream.  OKPZ_EOVERFLOW if the
+ * MCS counter would reach 2^30.
+ */
+int okpz_run(okpz_lattice *lat, uint64_t n_mcs, double p, double q);
+
+/* Exact height moments of the current state.  Synchronous. */
+int okpz_measure(okpz_lattice *lat, okpz_moments *out);
+
+/* Store the current state as the reference time s for okpz_autocorr. */
+int okpz_snapshot(okpz_lattice *lat);
+
+/* C_h(t, s) against the snapshot (OKPZ_ESTATE if none).  Synchronous. */
+int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out);
+
+/* Copy the state to host `sites` (L*L bytes).  Synchronous. */
+int okpz_get_sites(okpz_lattice *lat, uint8_t *sites);
+
+/*
+ * Copy the w x h window with corner (x0, y0) (periodic) to host `sites`
+ * (w*h bytes, index j*w + i is site (x0+i, y0+j) mod L).  Synchronous.
+ */
+int okpz_get_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h,
+                    uint8_t *sites);
+
+/*
+ * Overwrite the w x h window at (x0, y0) from host `sites` (same layout as
+ * okpz_get_window).  The whole resulting state is NOT re-validated (this is
+ * meant for small, known perturbations of large lattices); the caller is
+ * responsible for keeping it a valid surface.  Drops any snapshot.
+ */
+int okpz_set_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h,
+                    const uint8_t *sites);
+
+/* Heights (gauge h(0,0) = 0) to host `heights` (L*L int32).  Synchronous. */
+int okpz_get_heights(okpz_lattice *lat, int32_t *heights);
+
+/* Packed lattice words to / from host (L*L/16 uint32).  Synchronous. */
+int okpz_get_words(okpz_lattice *lat, uint32_t *words);
+
+/* Device pointer and size of the packed lattice (owned by the handle). */
+int okpz_device_words(okpz_lattice *lat, void **dev_words, size_t *nbytes);
+
+/* MCS counter (number of MCS applied since the flat start). */
+int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs);
+
+/* Copy the parameters the handle was created with. */
+int okpz_get_params(const okpz_lattice *lat, okpz_params *out);
+
+/* Wait for all queued work of the handle. */
+int okpz_sync(okpz_lattice *lat);
+
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch of the device-step kernel (four per MCS) and of the
+ * measurement kernels.  okpz_timing(lat, 1) enables and zeroes the
+ * counters; okpz_timing(lat, 0) disables.  okpz_get_timing synchronises and
+ * returns total milliseconds and launch counts.
+ */
+int okpz_timing(okpz_lattice *lat, int enable);
+int okpz_get_timing(okpz_lattice *lat, double *step_ms, uint64_t *step_launches,
+                    double *measure_ms, uint64_t *measure_launches);
+
+/*
+ * Device Philox4x32-10 (SC'11) on n counters: ctr and out are host arrays of
+ * 4*n uint32 (counter words c0..c3 / output words per block), key = (k0, k1).
+ * For testing the generator the step kernel uses.  Synchronous.
+ */
+int okpz_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OKPZ_H */

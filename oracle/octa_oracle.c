@@ -437,6 +437,11 @@ typedef struct {
  */
 static int footprint_ok(const orc_dtr_cfg *cfg, uint8_t *valid, uint32_t X0, uint32_t Y0)
 {
+    /* footprint entirely outside the window: nothing to check or invalidate */
+    uint32_t lx0 = (X0 + cfg->L - cfg->wx0 % cfg->L) % cfg->L;
+    uint32_t ly0 = (Y0 + cfg->L - cfg->wy0 % cfg->L) % cfg->L;
+    if ((lx0 >= cfg->W && lx0 + cfg->Dx < cfg->L) || (ly0 >= cfg->H && ly0 + cfg->Dy < cfg->L))
+        return 0;
     int ok = 1;
     for (uint32_t v = 0; v <= cfg->Dy && ok; ++v)
         for (uint32_t u = 0; u <= cfg->Dx; ++u) {

@@ -1,0 +1,304 @@
+"""MI355X-native octahedron-model KPZ simulator (DTr domain decomposition).
+
+Thin ctypes binding of the C ABI in ``include/okpz.h`` (library
+``paper_1705_01022_amd/lib/libokpz.so``, built for gfx950 by
+``paper_1705_01022_amd.build``).  Every step of the simulation runs in the
+library's HIP kernels; this module only marshals arguments.  There is no CPU
+fallback: if the library is missing, ``load()`` raises.
+
+Method: Kelling, Odor, Gemming, arXiv:1705.01022 -- random-sequential updates of
+the octahedron model (Sec. 2.1) parallelised by double tiling with a random
+origin each MCS (DTr, Sec. 3) at device level and single-hit DT / DB / DTr at
+block level (Sec. 3.1); roughness W^2 and height autocorrelation C_h (Sec. 2.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libokpz.so")
+
+OK, EINVAL, ENOMEM, EHIP, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5
+BLOCK_DT, BLOCK_DB, BLOCK_DTR = 0, 1, 2
+ORIGIN_RANDOM, ORIGIN_FIXED, ORIGIN_COARSE = 0, 1, 2
+SCHEMES = {"DT": BLOCK_DT, "DB": BLOCK_DB, "DTR": BLOCK_DTR, "DTr": BLOCK_DTR}
+
+
+class OkpzError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        msg = "%s failed: %s (%d)" % (what, _strerror(status), status)
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_uint32),
+        ("dom_x", ctypes.c_uint32),
+        ("dom_y", ctypes.c_uint32),
+        ("cell_x", ctypes.c_uint32),
+        ("cell_y", ctypes.c_uint32),
+        ("block_scheme", ctypes.c_int32),
+        ("seed", ctypes.c_uint32),
+        ("stream", ctypes.c_uint32),
+        ("origin_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class I128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_int64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class Moments(ctypes.Structure):
+    _fields_ = [
+        ("mcs", ctypes.c_uint64),
+        ("n_even", ctypes.c_int64),
+        ("n_odd", ctypes.c_int64),
+        ("s1_even", I128),
+        ("s1_odd", I128),
+        ("s2_even", I128),
+        ("s2_odd", I128),
+        ("w2", ctypes.c_double),
+        ("w2_sub", ctypes.c_double),
+    ]
+
+
+class Correlation(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_uint64),
+        ("s", ctypes.c_uint64),
+        ("s_ts", I128),
+        ("s1_t", I128),
+        ("s1_s", I128),
+        ("c_h", ctypes.c_double),
+    ]
+
+
+# name -> (restype, argtypes); the same names as include/okpz.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "okpz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "okpz_last_error": (ctypes.c_char_p, []),
+    "okpz_version": (ctypes.c_int, []),
+    "okpz_validate": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    "okpz_create": (ctypes.c_int, [ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
+    "okpz_create_external": (ctypes.c_int, [ctypes.POINTER(Params), _P, _P, ctypes.c_size_t,
+                                             ctypes.POINTER(_P)]),
+    "okpz_destroy": (ctypes.c_int, [_P]),
+    "okpz_init_flat": (ctypes.c_int, [_P]),
+    "okpz_init_from_host": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "okpz_run": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_double, ctypes.c_double]),
+    "okpz_measure": (ctypes.c_int, [_P, ctypes.POINTER(Moments)]),
+    "okpz_snapshot": (ctypes.c_int, [_P]),
+    "okpz_autocorr": (ctypes.c_int, [_P, ctypes.POINTER(Correlation)]),
+    "okpz_get_sites": (ctypes.c_int, [_P, _P]),
+    "okpz_get_window": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, _P]),
+    "okpz_set_window": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, _P]),
+    "okpz_get_heights": (ctypes.c_int, [_P, _P]),
+    "okpz_get_words": (ctypes.c_int, [_P, _P]),
+    "okpz_device_words": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
+    "okpz_get_mcs": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    "okpz_get_params": (ctypes.c_int, [_P, ctypes.POINTER(Params)]),
+    "okpz_sync": (ctypes.c_int, [_P]),
+    "okpz_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "okpz_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "okpz_philox": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _P, _P, ctypes.c_size_t]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("HIP library %s is missing: run `python -m paper_1705_01022_amd.build` "
+                              "(there is no CPU fallback)" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load().okpz_strerror(status).decode()
+    except Exception:  # noqa: BLE001 - message formatting only
+        return "status"
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        detail = load().okpz_last_error().decode() if status == EHIP else ""
+        raise OkpzError(status, what, detail)
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def params(L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0, origin_mode=ORIGIN_RANDOM) -> Params:
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    return Params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode, 0)
+
+
+def validate(prm: Params) -> int:
+    n = ctypes.c_size_t(0)
+    st = load().okpz_validate(ctypes.byref(prm), ctypes.byref(n))
+    return n.value if st == OK else st
+
+
+def _to_int(v: I128) -> int:
+    return v.value()
+
+
+class Lattice:
+    """One octahedron-model lattice resident on the GPU."""
+
+    def __init__(self, L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0,
+                 origin_mode=ORIGIN_RANDOM, hip_stream=None, device_buffer=None):
+        lib = load()
+        self.prm = params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode)
+        self.L = L
+        h = ctypes.c_void_p()
+        s = ctypes.c_void_p(hip_stream) if hip_stream else None
+        if device_buffer is not None:
+            ptr, nbytes = device_buffer
+            _check(lib.okpz_create_external(ctypes.byref(self.prm), s, ctypes.c_void_p(ptr), nbytes,
+                                            ctypes.byref(h)), "okpz_create_external")
+        else:
+            _check(lib.okpz_create(ctypes.byref(self.prm), s, ctypes.byref(h)), "okpz_create")
+        self._h = h
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().okpz_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state
+    def init_flat(self):
+        _check(load().okpz_init_flat(self._h), "okpz_init_flat")
+
+    def init_from_host(self, sites: np.ndarray, mcs: int = 0):
+        s = np.ascontiguousarray(sites, dtype=np.uint8)
+        assert s.shape == (self.L, self.L)
+        _check(load().okpz_init_from_host(self._h, _ptr(s), mcs), "okpz_init_from_host")
+
+    @property
+    def mcs(self) -> int:
+        v = ctypes.c_uint64()
+        _check(load().okpz_get_mcs(self._h, ctypes.byref(v)), "okpz_get_mcs")
+        return v.value
+
+    def run(self, n_mcs: int, p: float, q: float):
+        _check(load().okpz_run(self._h, n_mcs, p, q), "okpz_run")
+
+    def sync(self):
+        _check(load().okpz_sync(self._h), "okpz_sync")
+
+    # -- observables
+    def measure(self) -> dict:
+        m = Moments()
+        _check(load().okpz_measure(self._h, ctypes.byref(m)), "okpz_measure")
+        return {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
+                "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
+                "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
+                "w2": m.w2, "w2_sub": m.w2_sub}
+
+    def snapshot(self):
+        _check(load().okpz_snapshot(self._h), "okpz_snapshot")
+
+    def autocorr(self) -> dict:
+        c = Correlation()
+        _check(load().okpz_autocorr(self._h, ctypes.byref(c)), "okpz_autocorr")
+        return {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
+                "s1_s": _to_int(c.s1_s), "c_h": c.c_h}
+
+    # -- export / import
+    def sites(self) -> np.ndarray:
+        out = np.zeros((self.L, self.L), dtype=np.uint8)
+        _check(load().okpz_get_sites(self._h, _ptr(out)), "okpz_get_sites")
+        return out
+
+    def window(self, x0: int, y0: int, w: int, h: int) -> np.ndarray:
+        out = np.zeros((h, w), dtype=np.uint8)
+        _check(load().okpz_get_window(self._h, x0, y0, w, h, _ptr(out)), "okpz_get_window")
+        return out
+
+    def set_window(self, x0: int, y0: int, sites: np.ndarray):
+        s = np.ascontiguousarray(sites, dtype=np.uint8)
+        h, w = s.shape
+        _check(load().okpz_set_window(self._h, x0, y0, w, h, _ptr(s)), "okpz_set_window")
+
+    def heights(self) -> np.ndarray:
+        out = np.zeros((self.L, self.L), dtype=np.int32)
+        _check(load().okpz_get_heights(self._h, _ptr(out)), "okpz_get_heights")
+        return out
+
+    def words(self) -> np.ndarray:
+        out = np.zeros(self.L * self.L // 16, dtype=np.uint32)
+        _check(load().okpz_get_words(self._h, _ptr(out)), "okpz_get_words")
+        return out
+
+    def device_words(self):
+        p, n = ctypes.c_void_p(), ctypes.c_size_t()
+        _check(load().okpz_device_words(self._h, ctypes.byref(p), ctypes.byref(n)),
+               "okpz_device_words")
+        return p.value, n.value
+
+    # -- timing
+    def timing(self, enable: bool = True):
+        _check(load().okpz_timing(self._h, int(enable)), "okpz_timing")
+
+    def get_timing(self) -> dict:
+        sm, mm = ctypes.c_double(), ctypes.c_double()
+        sn, mn = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().okpz_get_timing(self._h, ctypes.byref(sm), ctypes.byref(sn), ctypes.byref(mm),
+                                      ctypes.byref(mn)), "okpz_get_timing")
+        return {"step_ms": sm.value, "step_launches": sn.value,
+                "measure_ms": mm.value, "measure_launches": mn.value}
+
+
+def philox(k0: int, k1: int, counters: np.ndarray) -> np.ndarray:
+    """Device Philox4x32-10 blocks for an (n, 4) uint32 array of counters."""
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    _check(load().okpz_philox(k0, k1, _ptr(c), _ptr(out), c.shape[0]), "okpz_philox")
+    return out
+
+
+def exported_symbols() -> list:
+    return sorted(_SIGS)

@@ -1,0 +1,809 @@
+// C ABI of the MI355X octahedron-model simulator: host side.
+//
+// Each Monte Carlo step (MCS) draws a fresh random origin and a random
+// order of the four domain sets of the double tiling (Sec. 3, DTr) and
+// launches the device-step kernel once per set; the kernel boundary is the
+// device-wide synchronisation between sets (Sec. 3.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/okpz.h"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+using namespace okpz;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return OKPZ_EHIP;
+}
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+uint32_t ilog2(uint64_t v)
+{
+    uint32_t r = 0;
+    while ((uint64_t(1) << r) < v) ++r;
+    return r;
+}
+
+constexpr uint32_t kMaxL = 1u << 17;
+constexpr uint32_t kMaxLds = 64u * 1024u;
+constexpr uint64_t kMcsLimit = uint64_t(1) << 30;
+
+struct TimedPair {
+    hipEvent_t start, stop;
+    int kind;  // 0 step, 1 measure
+};
+
+}  // namespace
+
+struct okpz_lattice {
+    okpz_params prm;
+    hipStream_t stream = nullptr;
+    uint32_t *words = nullptr;
+    bool external = false;
+    uint64_t nwords = 0;
+    uint64_t mcs = 0;
+    // measurement
+    int32_t *h0 = nullptr;
+    int32_t *h0s = nullptr;
+    uint32_t *snap = nullptr;
+    int64_t *partial = nullptr;
+    int64_t *reduced = nullptr;
+    int64_t *host_out = nullptr;  // pinned
+    bool has_snap = false;
+    uint64_t snap_mcs = 0;
+    __int128 snap_s1 = 0;
+    // timing
+    bool timing = false;
+    std::vector<TimedPair> pairs;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+int check_params(const okpz_params *p)
+{
+    if (!p) return OKPZ_EINVAL;
+    if (!is_pow2(p->L) || p->L < 16 || p->L > kMaxL) return OKPZ_EINVAL;
+    if (!is_pow2(p->dom_x) || !is_pow2(p->dom_y) || p->dom_x < 4 || p->dom_y < 4) return OKPZ_EINVAL;
+    if (2 * p->dom_x > p->L || 2 * p->dom_y > p->L) return OKPZ_EINVAL;
+    if (!is_pow2(p->cell_x) || !is_pow2(p->cell_y) || p->cell_x < 2 || p->cell_y < 2) return OKPZ_EINVAL;
+    if (p->cell_x > 64 || p->cell_y > 64 || p->cell_x > p->dom_x || p->cell_y > p->dom_y) return OKPZ_EINVAL;
+    if (p->block_scheme < OKPZ_BLOCK_DT || p->block_scheme > OKPZ_BLOCK_DTR) return OKPZ_EINVAL;
+    if (p->origin_mode < OKPZ_ORIGIN_RANDOM || p->origin_mode > OKPZ_ORIGIN_COARSE) return OKPZ_EINVAL;
+    if (p->reserved != 0) return OKPZ_EINVAL;
+    const uint64_t lds = uint64_t(p->dom_x / 4 + 1) * (p->dom_y / 4 + 1) * 4;
+    if (lds > kMaxLds) return OKPZ_EINVAL;
+    const uint64_t ncell = uint64_t(p->dom_x / p->cell_x) * (p->dom_y / p->cell_y);
+    if (ncell > 4096u) return OKPZ_EINVAL;  // at most 16 cells per lane of a 256-thread workgroup
+    return OKPZ_OK;
+}
+
+// ---------------------------------------------------------------- exact rounding
+// Correctly rounded (nearest, ties to even) conversion of a 128-bit integer.
+double i128_to_double(__int128 v)
+{
+    if (v == 0) return 0.0;
+    const bool neg = v < 0;
+    unsigned __int128 m = neg ? (unsigned __int128)(-(v + 1)) + 1 : (unsigned __int128)v;
+    int msb = 127;
+    while (!((m >> msb) & 1)) --msb;
+    double r;
+    if (msb <= 52) {
+        r = (double)(uint64_t)m;
+    } else {
+        const int drop = msb - 52;  // keep 53 significant bits
+        unsigned __int128 keep = m >> drop;
+        const unsigned __int128 rem = m & (((unsigned __int128)1 << drop) - 1);
+        const unsigned __int128 half = (unsigned __int128)1 << (drop - 1);
+        if (rem > half || (rem == half && (keep & 1))) ++keep;
+        r = std::ldexp((double)(uint64_t)keep, drop);  // keep <= 2^53, exact
+    }
+    return neg ? -r : r;
+}
+
+__int128 pair_to_i128(const int64_t *p) { return ((__int128)p[1] << 64) | (uint64_t)p[0]; }
+
+okpz_i128 to_abi(__int128 v)
+{
+    okpz_i128 r;
+    r.lo = (uint64_t)v;
+    r.hi = (int64_t)(v >> 64);
+    return r;
+}
+
+// ---------------------------------------------------------------- MCS draw
+// Origin uniform over all sites and one of the 24 orders of the four domain
+// sets (Sec. 3: DT shuffles the set order each MCS; DTr moves the origin),
+// from the Philox block (0, 0xFFFFFFFF, 0xFFFFFFFF, 4*MCS); the order is
+// entry floor(24 w2 / 2^32) of the permutations in lexicographic order.
+struct McsDraw {
+    uint32_t ox, oy;
+    int perm[4];
+};
+
+McsDraw mcs_draw(const okpz_params &p, uint64_t m)
+{
+    const u32x4 w = philox4x32_10(p.seed, p.stream, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)(m << 2));
+    McsDraw d;
+    d.ox = w.x & (p.L - 1);
+    d.oy = w.y & (p.L - 1);
+    if (p.origin_mode == OKPZ_ORIGIN_FIXED) d.ox = d.oy = 0;
+    if (p.origin_mode == OKPZ_ORIGIN_COARSE) {
+        d.ox &= ~3u;
+        d.oy &= ~3u;
+    }
+    const uint32_t pick = (uint32_t)(((uint64_t)w.z * 24u) >> 32);
+    int perm[4] = {0, 1, 2, 3};
+    for (uint32_t i = 0; i < pick; ++i) std::next_permutation(perm, perm + 4);
+    std::memcpy(d.perm, perm, sizeof(perm));
+    return d;
+}
+
+// ---------------------------------------------------------------- lane-draw shape
+struct LaneShape {
+    uint32_t s_bits, F_log2;
+    bool accept;
+    uint64_t P, Q;  // thresholds on the (A+32)-bit acceptance variate
+};
+
+bool prob01(double v) { return v == 0.0 || v == 1.0; }
+
+LaneShape lane_shape(const okpz_params &p, double pd, double qr)
+{
+    LaneShape ls;
+    const uint32_t sites = p.block_scheme == OKPZ_BLOCK_DB ? p.cell_x * p.cell_y : p.cell_x * p.cell_y / 4;
+    ls.s_bits = ilog2(sites);
+    ls.accept = !(prob01(pd) && prob01(qr));
+    if (ls.accept) {
+        const uint32_t F = 1u << ilog2(ls.s_bits + 8);
+        ls.F_log2 = ilog2(F);
+        const uint32_t A = F - ls.s_bits;
+        const double scale = std::ldexp(1.0, (int)(A + 32));
+        const uint64_t full = uint64_t(1) << (A + 32);
+        const double pp = std::floor(pd * scale + 0.5), qq = std::floor(qr * scale + 0.5);
+        ls.P = pp >= (double)full ? full : (uint64_t)pp;
+        ls.Q = qq >= (double)full ? full : (uint64_t)qq;
+    } else {
+        ls.F_log2 = ilog2(std::max<uint32_t>(ls.s_bits, 1));
+        ls.P = ls.Q = 0;
+    }
+    return ls;
+}
+
+// ---------------------------------------------------------------- launch helpers
+void begin_timed(okpz_lattice *lat, int kind, TimedPair &tp)
+{
+    tp.kind = kind;
+    if (!lat->timing) return;
+    (void)hipEventCreate(&tp.start);
+    (void)hipEventCreate(&tp.stop);
+    (void)hipEventRecord(tp.start, lat->stream);
+}
+
+void end_timed(okpz_lattice *lat, TimedPair &tp)
+{
+    if (!lat->timing) return;
+    (void)hipEventRecord(tp.stop, lat->stream);
+    lat->pairs.push_back(tp);
+}
+
+template <int SCHEME, bool ACCEPT>
+int launch_step_cpt(uint32_t cpt, uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
+{
+    switch (cpt) {
+    case 1: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 1>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 2>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 4>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    case 8: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 8>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    case 16: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 16>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    default: return OKPZ_EINVAL;
+    }
+    return OKPZ_OK;
+}
+
+int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
+{
+    const okpz_params &p = lat->prm;
+    const uint32_t ncell = a.ncell;
+    // workgroups of at most 256 threads (one wave per SIMD); up to 16 cells per lane
+    uint32_t cpt = 1, nt;
+    if (ncell <= 256) {
+        nt = std::max<uint32_t>(64, ncell);
+    } else {
+        cpt = ncell / 256;
+        nt = 256;
+    }
+    if (cpt > 16) return OKPZ_EINVAL;
+    const uint32_t ntiles = (p.L / (2 * p.dom_x)) * (p.L / (2 * p.dom_y));
+    const size_t lds = size_t(a.pitch) * a.Wy * sizeof(uint32_t);
+    int rc;
+    switch (p.block_scheme * 2 + (accept ? 1 : 0)) {
+    case 0: rc = launch_step_cpt<kDT, false>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    case 1: rc = launch_step_cpt<kDT, true>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    case 2: rc = launch_step_cpt<kDB, false>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    case 3: rc = launch_step_cpt<kDB, true>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    case 4: rc = launch_step_cpt<kDTR, false>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    default: rc = launch_step_cpt<kDTR, true>(cpt, nt, ntiles, lds, lat->stream, a); break;
+    }
+    if (rc != OKPZ_OK) return rc;
+    HIP_TRY(hipGetLastError());
+    return OKPZ_OK;
+}
+
+StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double pd, double qr)
+{
+    const okpz_params &p = lat->prm;
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.words = lat->words;
+    a.lw_log2 = ilog2(p.L / 4);
+    a.lw_mask = p.L / 4 - 1;
+    a.L_mask = p.L - 1;
+    a.Dx = p.dom_x;
+    a.Dy = p.dom_y;
+    a.log2Cx = ilog2(p.cell_x);
+    a.log2Cy = ilog2(p.cell_y);
+    a.log2ncx = ilog2(p.dom_x / p.cell_x);
+    a.ncell = (p.dom_x / p.cell_x) * (p.dom_y / p.cell_y);
+    a.log2ntx = ilog2(p.L / (2 * p.dom_x));
+    a.key0 = p.seed;
+    a.key1 = p.stream;
+    a.s_bits = ls.s_bits;
+    a.F_log2 = ls.F_log2;
+    a.rounds = p.cell_x * p.cell_y;
+    a.Wx = p.dom_x / 4 + 1;
+    a.Wy = p.dom_y / 4 + 1;
+    a.pitch = a.Wx;
+    a.dep_always = pd == 1.0;
+    a.rem_always = qr == 1.0;
+    a.P_hi = (uint32_t)(ls.P >> 32);
+    a.P_lo = (uint32_t)ls.P;
+    a.Q_hi = (uint32_t)(ls.Q >> 32);
+    a.Q_lo = (uint32_t)ls.Q;
+    return a;
+}
+
+int fill_flat(okpz_lattice *lat)
+{
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(4096, (lat->nwords + 255) / 256);
+    hipLaunchKernelGGL(fill_words_kernel, dim3(blocks), dim3(256), 0, lat->stream, lat->words, lat->nwords,
+                       kFlatWord);
+    HIP_TRY(hipGetLastError());
+    lat->mcs = 0;
+    lat->has_snap = false;
+    return OKPZ_OK;
+}
+
+// Heights of the current words into h0 (anchors) and per-row partials, then
+// the exact totals into lat->host_out (10 or 5x2 int64).  cross: also sum
+// h_t h_s against the snapshot.
+int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_dst)
+{
+    const okpz_params &p = lat->prm;
+    const uint32_t lw_log2 = ilog2(p.L / 4);
+    TimedPair tp;
+    begin_timed(lat, 1, tp);
+    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, lat->stream, src, p.L, lw_log2, h0_dst);
+    if (cross)
+        hipLaunchKernelGGL((rows_kernel<true>), dim3(p.L / 4), dim3(kMeasureThreads), 0, lat->stream, src,
+                           h0_dst, lat->snap, lat->h0s, p.L, lw_log2, lat->partial);
+    else
+        hipLaunchKernelGGL((rows_kernel<false>), dim3(p.L / 4), dim3(kMeasureThreads), 0, lat->stream, src,
+                           h0_dst, nullptr, nullptr, p.L, lw_log2, lat->partial);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, lat->stream, lat->partial, p.L / 4, lat->reduced);
+    end_timed(lat, tp);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(lat->host_out, lat->reduced, 2 * kMomentFields * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+void fill_moments(const okpz_lattice *lat, okpz_moments *out)
+{
+    const uint64_t L = lat->prm.L;
+    const int64_t *r = lat->host_out;
+    const __int128 s1e = pair_to_i128(r + 0), s1o = pair_to_i128(r + 2);
+    const __int128 s2e = pair_to_i128(r + 4), s2o = pair_to_i128(r + 6);
+    const __int128 n = (__int128)L * L, ne = n / 2, no = n / 2;
+    out->mcs = lat->mcs;
+    out->n_even = (int64_t)ne;
+    out->n_odd = (int64_t)no;
+    out->s1_even = to_abi(s1e);
+    out->s1_odd = to_abi(s1o);
+    out->s2_even = to_abi(s2e);
+    out->s2_odd = to_abi(s2o);
+    const int sh = 4 * (int)ilog2(L);  // N^2 = 2^(4 log2 L)
+    const __int128 s1 = s1e + s1o, s2 = s2e + s2o;
+    out->w2 = std::ldexp(i128_to_double(n * s2 - s1 * s1), -sh);
+    // (var_e + var_o)/2 = 2 [(ne s2e - s1e^2) + (no s2o - s1o^2)] / L^4
+    out->w2_sub = std::ldexp(i128_to_double(2 * ((ne * s2e - s1e * s1e) + (no * s2o - s1o * s1o))), -sh);
+}
+
+// host packing / unpacking
+void pack_sites(const uint8_t *sites, uint32_t L, uint32_t *words)
+{
+    const uint32_t lw = L / 4;
+    std::memset(words, 0, sizeof(uint32_t) * (size_t)lw * lw);
+    for (uint32_t y = 0; y < L; ++y)
+        for (uint32_t x = 0; x < L; ++x) {
+            const uint8_t v = sites[(size_t)y * L + x];
+            const uint32_t bit = 4 * (y & 3) + (x & 3);
+            uint32_t &w = words[(size_t)(y >> 2) * lw + (x >> 2)];
+            w |= (uint32_t)(v & 1) << bit;
+            w |= (uint32_t)((v >> 1) & 1) << (16 + bit);
+        }
+}
+
+inline uint8_t site_of(uint32_t w, uint32_t x, uint32_t y)
+{
+    const uint32_t bit = 4 * (y & 3) + (x & 3);
+    return (uint8_t)(((w >> bit) & 1) | (((w >> (16 + bit)) & 1) << 1));
+}
+
+bool valid_surface(const uint8_t *s, uint32_t L)
+{
+    for (size_t i = 0; i < (size_t)L * L; ++i)
+        if (s[i] & ~3u) return false;
+    std::vector<uint32_t> col(L, 0);
+    for (uint32_t y = 0; y < L; ++y) {
+        uint32_t row = 0;
+        for (uint32_t x = 0; x < L; ++x) {
+            row += s[(size_t)y * L + x] & 1;
+            col[x] += (s[(size_t)y * L + x] >> 1) & 1;
+        }
+        if (2 * row != L) return false;
+    }
+    for (uint32_t x = 0; x < L; ++x)
+        if (2 * col[x] != L) return false;
+    for (uint32_t y = 0; y < L; ++y) {
+        const uint32_t ym = (y + L - 1) & (L - 1);
+        for (uint32_t x = 0; x < L; ++x) {
+            const uint32_t xm = (x + L - 1) & (L - 1);
+            const int lhs = (s[(size_t)ym * L + x] & 1) + ((s[(size_t)y * L + x] >> 1) & 1);
+            const int rhs = ((s[(size_t)y * L + xm] >> 1) & 1) + (s[(size_t)y * L + x] & 1);
+            if (lhs != rhs) return false;
+        }
+    }
+    return true;
+}
+
+// copy word rows [wy0, wy0+nwy) x word columns [wx0, wx0+nwx) (periodic) to host
+int read_word_block(okpz_lattice *lat, uint32_t wx0, uint32_t wy0, uint32_t nwx, uint32_t nwy,
+                    std::vector<uint32_t> &buf)
+{
+    const uint32_t lw = lat->prm.L / 4;
+    buf.assign((size_t)nwx * nwy, 0);
+    for (uint32_t r = 0; r < nwy; ++r) {
+        const uint32_t gy = (wy0 + r) % lw;
+        uint32_t done = 0;
+        while (done < nwx) {
+            const uint32_t gx = (wx0 + done) % lw;
+            const uint32_t run = std::min(nwx - done, lw - gx);
+            HIP_TRY(hipMemcpyAsync(&buf[(size_t)r * nwx + done], lat->words + (size_t)gy * lw + gx,
+                                   run * sizeof(uint32_t), hipMemcpyDeviceToHost, lat->stream));
+            done += run;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+int write_word_block(okpz_lattice *lat, uint32_t wx0, uint32_t wy0, uint32_t nwx, uint32_t nwy,
+                     const std::vector<uint32_t> &buf)
+{
+    const uint32_t lw = lat->prm.L / 4;
+    for (uint32_t r = 0; r < nwy; ++r) {
+        const uint32_t gy = (wy0 + r) % lw;
+        uint32_t done = 0;
+        while (done < nwx) {
+            const uint32_t gx = (wx0 + done) % lw;
+            const uint32_t run = std::min(nwx - done, lw - gx);
+            HIP_TRY(hipMemcpyAsync(lat->words + (size_t)gy * lw + gx, &buf[(size_t)r * nwx + done],
+                                   run * sizeof(uint32_t), hipMemcpyHostToDevice, lat->stream));
+            done += run;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+void release(okpz_lattice *lat)
+{
+    if (!lat) return;
+    for (auto &tp : lat->pairs) {
+        (void)hipEventDestroy(tp.start);
+        (void)hipEventDestroy(tp.stop);
+    }
+    if (!lat->external && lat->words) (void)hipFree(lat->words);
+    if (lat->h0) (void)hipFree(lat->h0);
+    if (lat->h0s) (void)hipFree(lat->h0s);
+    if (lat->snap) (void)hipFree(lat->snap);
+    if (lat->partial) (void)hipFree(lat->partial);
+    if (lat->reduced) (void)hipFree(lat->reduced);
+    if (lat->host_out) (void)hipHostFree(lat->host_out);
+    delete lat;
+}
+
+int create_common(const okpz_params *params, void *hip_stream, void *dev_words, size_t nbytes,
+                  okpz_lattice **out)
+{
+    if (!out) return OKPZ_EINVAL;
+    *out = nullptr;
+    const int rc = check_params(params);
+    if (rc != OKPZ_OK) return rc;
+    const uint64_t need = (uint64_t)params->L * params->L / 4;
+    okpz_lattice *lat = new (std::nothrow) okpz_lattice();
+    if (!lat) return OKPZ_ENOMEM;
+    lat->prm = *params;
+    lat->stream = (hipStream_t)hip_stream;
+    lat->nwords = need / 4;
+    if (dev_words) {
+        if (nbytes < need || ((uintptr_t)dev_words & 255u)) {
+            delete lat;
+            return OKPZ_EINVAL;
+        }
+        lat->words = (uint32_t *)dev_words;
+        lat->external = true;
+    } else if (hipMalloc(&lat->words, need) != hipSuccess) {
+        lat->words = nullptr;
+        release(lat);
+        return OKPZ_ENOMEM;
+    }
+    const uint32_t L = params->L;
+    if (hipMalloc(&lat->h0, L * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&lat->partial, (size_t)(L / 4) * kMomentFields * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&lat->reduced, 2 * kMomentFields * sizeof(int64_t)) != hipSuccess ||
+        hipHostMalloc(&lat->host_out, 2 * kMomentFields * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        release(lat);
+        return OKPZ_ENOMEM;
+    }
+    const int frc = fill_flat(lat);
+    if (frc != OKPZ_OK) {
+        release(lat);
+        return frc;
+    }
+    *out = lat;
+    return OKPZ_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+const char *okpz_strerror(int status)
+{
+    switch (status) {
+    case OKPZ_OK: return "ok";
+    case OKPZ_EINVAL: return "invalid argument";
+    case OKPZ_ENOMEM: return "out of memory";
+    case OKPZ_EHIP: return "HIP runtime error";
+    case OKPZ_EOVERFLOW: return "counter or reduction overflow";
+    case OKPZ_ESTATE: return "invalid state for this call";
+    default: return "unknown status";
+    }
+}
+
+const char *okpz_last_error(void) { return g_last_error.c_str(); }
+
+int okpz_version(void) { return 100; }
+
+int okpz_validate(const okpz_params *params, size_t *nbytes)
+{
+    const int rc = check_params(params);
+    if (rc == OKPZ_OK && nbytes) *nbytes = (size_t)params->L * params->L / 4;
+    return rc;
+}
+
+int okpz_create(const okpz_params *params, void *hip_stream, okpz_lattice **out)
+{
+    return create_common(params, hip_stream, nullptr, 0, out);
+}
+
+int okpz_create_external(const okpz_params *params, void *hip_stream, void *dev_words, size_t nbytes,
+                         okpz_lattice **out)
+{
+    if (!dev_words) return OKPZ_EINVAL;
+    return create_common(params, hip_stream, dev_words, nbytes, out);
+}
+
+int okpz_destroy(okpz_lattice *lat)
+{
+    if (!lat) return OKPZ_EINVAL;
+    (void)hipStreamSynchronize(lat->stream);
+    release(lat);
+    return OKPZ_OK;
+}
+
+int okpz_init_flat(okpz_lattice *lat)
+{
+    if (!lat) return OKPZ_EINVAL;
+    return fill_flat(lat);
+}
+
+int okpz_init_from_host(okpz_lattice *lat, const uint8_t *sites, uint64_t mcs)
+{
+    if (!lat || !sites || mcs >= kMcsLimit) return OKPZ_EINVAL;
+    const uint32_t L = lat->prm.L;
+    if (!valid_surface(sites, L)) return OKPZ_EINVAL;
+    std::vector<uint32_t> w((size_t)L * L / 16);
+    pack_sites(sites, L, w.data());
+    HIP_TRY(hipMemcpyAsync(lat->words, w.data(), w.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->mcs = mcs;
+    lat->has_snap = false;
+    return OKPZ_OK;
+}
+
+int okpz_run(okpz_lattice *lat, uint64_t n_mcs, double p, double q)
+{
+    if (!lat) return OKPZ_EINVAL;
+    if (!(p >= 0.0 && p <= 1.0 && q >= 0.0 && q <= 1.0)) return OKPZ_EINVAL;
+    if (n_mcs > kMcsLimit || lat->mcs + n_mcs > kMcsLimit) return OKPZ_EOVERFLOW;
+    const LaneShape ls = lane_shape(lat->prm, p, q);
+    StepArgs a = base_args(lat, ls, p, q);
+    for (uint64_t i = 0; i < n_mcs; ++i) {
+        const uint64_t m = lat->mcs;
+        const McsDraw d = mcs_draw(lat->prm, m);
+        a.ox = d.ox;
+        a.oy = d.oy;
+        for (uint32_t k = 0; k < 4; ++k) {
+            a.set_a = (uint32_t)d.perm[k] & 1u;
+            a.set_b = (uint32_t)d.perm[k] >> 1;
+            a.c3 = (uint32_t)(m << 2) | k;
+            TimedPair tp;
+            begin_timed(lat, 0, tp);
+            const int rc = launch_step(lat, a, ls.accept);
+            end_timed(lat, tp);
+            if (rc != OKPZ_OK) return rc;
+        }
+        lat->mcs = m + 1;
+    }
+    return OKPZ_OK;
+}
+
+int okpz_measure(okpz_lattice *lat, okpz_moments *out)
+{
+    if (!lat || !out) return OKPZ_EINVAL;
+    const int rc = run_measure(lat, false, lat->words, lat->h0);
+    if (rc != OKPZ_OK) return rc;
+    fill_moments(lat, out);
+    return OKPZ_OK;
+}
+
+int okpz_snapshot(okpz_lattice *lat)
+{
+    if (!lat) return OKPZ_EINVAL;
+    const uint32_t L = lat->prm.L;
+    if (!lat->snap) {
+        if (hipMalloc(&lat->snap, (size_t)L * L / 4) != hipSuccess) {
+            lat->snap = nullptr;
+            return OKPZ_ENOMEM;
+        }
+        if (hipMalloc(&lat->h0s, L * sizeof(int32_t)) != hipSuccess) {
+            lat->h0s = nullptr;
+            return OKPZ_ENOMEM;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(lat->snap, lat->words, (size_t)L * L / 4, hipMemcpyDeviceToDevice, lat->stream));
+    const int rc = run_measure(lat, false, lat->snap, lat->h0s);
+    if (rc != OKPZ_OK) return rc;
+    lat->snap_s1 = pair_to_i128(lat->host_out + 0) + pair_to_i128(lat->host_out + 2);
+    lat->snap_mcs = lat->mcs;
+    lat->has_snap = true;
+    return OKPZ_OK;
+}
+
+int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out)
+{
+    if (!lat || !out) return OKPZ_EINVAL;
+    if (!lat->has_snap) return OKPZ_ESTATE;
+    const int rc = run_measure(lat, true, lat->words, lat->h0);
+    if (rc != OKPZ_OK) return rc;
+    const uint64_t L = lat->prm.L;
+    const __int128 n = (__int128)L * L;
+    const __int128 s1t = pair_to_i128(lat->host_out + 0) + pair_to_i128(lat->host_out + 2);
+    const __int128 sts = pair_to_i128(lat->host_out + 8);
+    out->t = lat->mcs;
+    out->s = lat->snap_mcs;
+    out->s_ts = to_abi(sts);
+    out->s1_t = to_abi(s1t);
+    out->s1_s = to_abi(lat->snap_s1);
+    out->c_h = std::ldexp(i128_to_double(n * sts - s1t * lat->snap_s1), -4 * (int)ilog2(L));
+    return OKPZ_OK;
+}
+
+int okpz_get_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h, uint8_t *sites)
+{
+    if (!lat || !sites) return OKPZ_EINVAL;
+    const uint32_t L = lat->prm.L;
+    if (w == 0 || h == 0 || w > L || h > L) return OKPZ_EINVAL;
+    x0 &= L - 1;
+    y0 &= L - 1;
+    const uint32_t wx0 = x0 >> 2, wy0 = y0 >> 2;
+    const uint32_t nwx = std::min(L / 4, ((x0 & 3) + w + 3) / 4);
+    const uint32_t nwy = std::min(L / 4, ((y0 & 3) + h + 3) / 4);
+    std::vector<uint32_t> buf;
+    const int rc = read_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    if (rc != OKPZ_OK) return rc;
+    for (uint32_t j = 0; j < h; ++j)
+        for (uint32_t i = 0; i < w; ++i) {
+            const uint32_t gx = (x0 + i) & (L - 1), gy = (y0 + j) & (L - 1);
+            const uint32_t bx = ((gx >> 2) - wx0) & (L / 4 - 1), by = ((gy >> 2) - wy0) & (L / 4 - 1);
+            sites[(size_t)j * w + i] = site_of(buf[(size_t)by * nwx + bx], gx, gy);
+        }
+    return OKPZ_OK;
+}
+
+int okpz_set_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h, const uint8_t *sites)
+{
+    if (!lat || !sites) return OKPZ_EINVAL;
+    const uint32_t L = lat->prm.L;
+    if (w == 0 || h == 0 || w > L || h > L) return OKPZ_EINVAL;
+    for (size_t i = 0; i < (size_t)w * h; ++i)
+        if (sites[i] & ~3u) return OKPZ_EINVAL;
+    x0 &= L - 1;
+    y0 &= L - 1;
+    const uint32_t wx0 = x0 >> 2, wy0 = y0 >> 2;
+    const uint32_t nwx = std::min(L / 4, ((x0 & 3) + w + 3) / 4);
+    const uint32_t nwy = std::min(L / 4, ((y0 & 3) + h + 3) / 4);
+    std::vector<uint32_t> buf;
+    int rc = read_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    if (rc != OKPZ_OK) return rc;
+    for (uint32_t j = 0; j < h; ++j)
+        for (uint32_t i = 0; i < w; ++i) {
+            const uint32_t gx = (x0 + i) & (L - 1), gy = (y0 + j) & (L - 1);
+            const uint32_t bx = ((gx >> 2) - wx0) & (L / 4 - 1), by = ((gy >> 2) - wy0) & (L / 4 - 1);
+            uint32_t &word = buf[(size_t)by * nwx + bx];
+            const uint32_t bit = 4 * (gy & 3) + (gx & 3);
+            const uint8_t v = sites[(size_t)j * w + i];
+            word &= ~((1u << bit) | (1u << (16 + bit)));
+            word |= ((uint32_t)(v & 1) << bit) | ((uint32_t)((v >> 1) & 1) << (16 + bit));
+        }
+    rc = write_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    if (rc == OKPZ_OK) lat->has_snap = false;
+    return rc;
+}
+
+int okpz_get_sites(okpz_lattice *lat, uint8_t *sites)
+{
+    if (!lat) return OKPZ_EINVAL;
+    return okpz_get_window(lat, 0, 0, lat->prm.L, lat->prm.L, sites);
+}
+
+int okpz_get_heights(okpz_lattice *lat, int32_t *heights)
+{
+    if (!lat || !heights) return OKPZ_EINVAL;
+    const uint32_t L = lat->prm.L;
+    std::vector<uint8_t> s((size_t)L * L);
+    const int rc = okpz_get_sites(lat, s.data());
+    if (rc != OKPZ_OK) return rc;
+    for (uint32_t y = 0; y < L; ++y) {
+        int32_t h = y == 0 ? 0 : heights[(size_t)(y - 1) * L] + 2 * ((s[(size_t)y * L] >> 1) & 1) - 1;
+        heights[(size_t)y * L] = h;
+        for (uint32_t x = 1; x < L; ++x) {
+            h += 2 * (s[(size_t)y * L + x] & 1) - 1;
+            heights[(size_t)y * L + x] = h;
+        }
+    }
+    return OKPZ_OK;
+}
+
+int okpz_get_words(okpz_lattice *lat, uint32_t *words)
+{
+    if (!lat || !words) return OKPZ_EINVAL;
+    HIP_TRY(hipMemcpyAsync(words, lat->words, lat->nwords * sizeof(uint32_t), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+int okpz_device_words(okpz_lattice *lat, void **dev_words, size_t *nbytes)
+{
+    if (!lat) return OKPZ_EINVAL;
+    if (dev_words) *dev_words = lat->words;
+    if (nbytes) *nbytes = lat->nwords * sizeof(uint32_t);
+    return OKPZ_OK;
+}
+
+int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs)
+{
+    if (!lat || !mcs) return OKPZ_EINVAL;
+    *mcs = lat->mcs;
+    return OKPZ_OK;
+}
+
+int okpz_get_params(const okpz_lattice *lat, okpz_params *out)
+{
+    if (!lat || !out) return OKPZ_EINVAL;
+    *out = lat->prm;
+    return OKPZ_OK;
+}
+
+int okpz_sync(okpz_lattice *lat)
+{
+    if (!lat) return OKPZ_EINVAL;
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+int okpz_timing(okpz_lattice *lat, int enable)
+{
+    if (!lat) return OKPZ_EINVAL;
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    for (auto &tp : lat->pairs) {
+        (void)hipEventDestroy(tp.start);
+        (void)hipEventDestroy(tp.stop);
+    }
+    lat->pairs.clear();
+    lat->timing = enable != 0;
+    return OKPZ_OK;
+}
+
+int okpz_get_timing(okpz_lattice *lat, double *step_ms, uint64_t *step_launches, double *measure_ms,
+                    uint64_t *measure_launches)
+{
+    if (!lat) return OKPZ_EINVAL;
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    double ms[2] = {0, 0};
+    uint64_t cnt[2] = {0, 0};
+    for (auto &tp : lat->pairs) {
+        float e = 0;
+        HIP_TRY(hipEventElapsedTime(&e, tp.start, tp.stop));
+        ms[tp.kind] += e;
+        cnt[tp.kind] += 1;
+    }
+    if (step_ms) *step_ms = ms[0];
+    if (step_launches) *step_launches = cnt[0];
+    if (measure_ms) *measure_ms = ms[1];
+    if (measure_launches) *measure_launches = cnt[1];
+    return OKPZ_OK;
+}
+
+int okpz_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, size_t n)
+{
+    if (!ctr || !out) return OKPZ_EINVAL;
+    if (n == 0) return OKPZ_OK;
+    uint32_t *dctr = nullptr, *dout = nullptr;
+    HIP_TRY(hipMalloc(&dctr, n * 4 * sizeof(uint32_t)));
+    if (hipMalloc(&dout, n * 4 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(dctr);
+        return OKPZ_ENOMEM;
+    }
+    int rc = OKPZ_OK;
+    hipError_t e = hipMemcpy(dctr, ctr, n * 4 * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nullptr, k0, k1, dctr,
+                           dout, (uint64_t)n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * 4 * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "okpz_philox");
+    (void)hipFree(dctr);
+    (void)hipFree(dout);
+    return rc;
+}
+
+}  // extern "C"
