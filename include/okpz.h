@@ -208,7 +208,8 @@ int okpz_get_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uin
  * Overwrite the w x h window at (x0, y0) from host `sites` (same layout as
  * okpz_get_window).  The whole resulting state is NOT re-validated (this is
  * meant for small, known perturbations of large lattices); the caller is
- * responsible for keeping it a valid surface.  Drops any snapshot.
+ * responsible for keeping it a valid surface.  A snapshot taken earlier is
+ * kept (it describes the earlier state).  Synchronous.
  */
 int okpz_set_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h,
                     const uint8_t *sites);

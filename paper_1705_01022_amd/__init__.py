@@ -123,9 +123,20 @@ _lib = None
 
 
 def load():
-    """Load the HIP library; raise if it has not been built."""
+    """Load the HIP library; raise if it has not been built.
+
+    torch is imported first when it is installed: its libraries load the HIP
+    runtime it ships with, and the library then binds to that same runtime (its
+    libamdhip64.so.7 dependency is satisfied by the already-loaded copy), so one
+    process never holds two HIP runtimes and torch tensors and streams can be
+    handed to the library.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("HIP library %s is missing: run `python -m paper_1705_01022_amd.build` "
                               "(there is no CPU fallback)" % LIB_PATH)
@@ -302,3 +313,13 @@ def philox(k0: int, k1: int, counters: np.ndarray) -> np.ndarray:
 
 def exported_symbols() -> list:
     return sorted(_SIGS)
+
+
+def hip_runtime_paths() -> list:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    out = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                out.add(line.split()[-1])
+    return sorted(out)

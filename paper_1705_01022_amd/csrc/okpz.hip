@@ -683,9 +683,7 @@ int okpz_set_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uin
             word &= ~((1u << bit) | (1u << (16 + bit)));
             word |= ((uint32_t)(v & 1) << bit) | ((uint32_t)((v >> 1) & 1) << (16 + bit));
         }
-    rc = write_word_block(lat, wx0, wy0, nwx, nwy, buf);
-    if (rc == OKPZ_OK) lat->has_snap = false;
-    return rc;
+    return write_word_block(lat, wx0, wy0, nwx, nwy, buf);
 }
 
 int okpz_get_sites(okpz_lattice *lat, uint8_t *sites)

@@ -104,3 +104,10 @@ def test_missing_library_fails_loudly(monkeypatch, okpz):
         pkg.load()
     monkeypatch.undo()
     importlib.reload(pkg)
+
+
+def test_single_hip_runtime(okpz):
+    # the library shares the HIP runtime torch loaded; never two in one process
+    okpz.load()
+    paths = okpz.hip_runtime_paths()
+    assert len(paths) == 1, paths
