@@ -5,7 +5,8 @@ flat zig-zag surface, DTrDB (device-level DTr, block-level single-hit dead
 border with delayed borders), 256 x 256-site device domains, TC=1,1 (8 x 8-site
 thread cells), p = 0.95, q = 0.05.  One step = one MCS (2^34 update attempts:
 4 device-step launches) + the exact W^2 measurement + the height
-autocorrelation C_h(t, s) against a snapshot taken after warm-up.
+autocorrelation C_h(t, s) against a snapshot taken after warm-up (one fused
+measurement pass).
 
 Prints ONE JSON line.  `value` is attempts/s over the timed steps (inputs
 resident in HBM); `roofline` reports the device-step kernel, timed with HIP
@@ -102,8 +103,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         lat.run(1, p, q)
-        mo = lat.measure()
-        ac = lat.autocorr()
+        mo, ac = lat.observe(True)
     lat.sync()
     elapsed = time.perf_counter() - t0
     tm = lat.get_timing()
@@ -140,7 +140,7 @@ def main():
         "config": {
             "workload": label,
             "L": L, "dom": [D, D], "cell": [C, C], "scheme": SCHEME_NAME[scheme], "p": p, "q": q,
-            "step": "1 MCS (L^2 attempts, 4 device-step launches) + exact W^2 + C_h(t,s)",
+            "step": "1 MCS (L^2 attempts, 4 device-step launches) + exact W^2 and C_h(t,s) in one pass",
             "parallelism": "single GPU",
         },
         "roofline": {

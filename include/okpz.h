@@ -16,9 +16,11 @@
  *     (one slope per direction is stored on the site, Sec. 3, DB scheme).
  *   - Host site arrays ("sites") are L*L bytes, index y*L + x,
  *     bit 0 = sx, bit 1 = sy, other bits zero.
- *   - Packed device layout ("words"): uint32 word (y/4)*(L/4) + x/4 holds the
- *     4x4 sites of its block (the paper's bit-coded lattice, Sec. 3.1):
- *     bit 4*(y%4) + x%4 is sx, bit 16 + 4*(y%4) + x%4 is sy.  L*L/4 bytes.
+ *   - Packed device layout ("words", 2 bits per site as in the paper's
+ *     bit-coded lattice, Sec. 3.1, arranged as row bit-planes): the lattice
+ *     is cut into blocks of 32 x 4 sites; block (x/32, y/4) has index
+ *     (y/4)*(L/32) + x/32 and owns 8 consecutive uint32 words: word y%4 holds
+ *     the sx bits of row y, word 4 + y%4 the sy bits, bit x%32.  L*L/4 bytes.
  *   - One MCS is L*L update attempts (Sec. 2.1, time unit).
  *   - Heights use the gauge h(0,0) = 0; every reported observable is
  *     invariant under the gauge.
@@ -69,10 +71,12 @@ extern "C" {
 /*
  * Simulation parameters.  Physics parameters (Sec. 3.1 notation DTrDT etc.
  * and TC=log2(cell_x/4),log2(cell_y/4)):
- *   L             lateral size, power of two, 16 <= L <= 2^17
+ *   L             lateral size, power of two, 64 <= L <= 2^17
  *   dom_x, dom_y  device domain (sub-tile) size in sites; tiles are
- *                 2*dom_x x 2*dom_y.  Powers of two, >= 4, 2*dom <= L,
- *                 (dom_x/4 + 1)*(dom_y/4 + 1)*4 bytes <= 64 KiB of LDS.
+ *                 2*dom_x x 2*dom_y.  Powers of two, >= 4, 2*dom <= L; the
+ *                 staged window, two bit planes of (dom_y + 4) rows by
+ *                 (dom_x/32 + 3) words (plus 8 bytes per cell for DB), must
+ *                 fit 160 KiB of LDS (dom_x <= 7936).
  *   cell_x,cell_y thread-cell size in sites, powers of two, 2 .. 64,
  *                 cell <= dom, at most 4096 cells per domain.
  *                 (TC=1,1 is 8 x 8 sites.)
@@ -194,6 +198,14 @@ int okpz_snapshot(okpz_lattice *lat);
 /* C_h(t, s) against the snapshot (OKPZ_ESTATE if none).  Synchronous. */
 int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out);
 
+/*
+ * Both observables from one pass over the lattice: the exact height moments
+ * (as okpz_measure) into *moments and, if corr is not NULL, C_h(t, s)
+ * against the snapshot (as okpz_autocorr; OKPZ_ESTATE without a snapshot).
+ * Synchronous.
+ */
+int okpz_observe(okpz_lattice *lat, okpz_moments *moments, okpz_correlation *corr);
+
 /* Copy the state to host `sites` (L*L bytes).  Synchronous. */
 int okpz_get_sites(okpz_lattice *lat, uint8_t *sites);
 
@@ -225,6 +237,15 @@ int okpz_device_words(okpz_lattice *lat, void **dev_words, size_t *nbytes);
 
 /* MCS counter (number of MCS applied since the flat start). */
 int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs);
+
+/*
+ * Workgroup size of the device-step kernel: 64, 128 or 256 threads, or 0 for
+ * the default (256).  Each thread then updates ncell / threads thread cells
+ * (at most 16, else OKPZ_EINVAL).  A physical mapping only: the simulated
+ * lattice does not depend on it (every random draw is keyed by cell, not by
+ * thread).  Chosen by an autotuner per domain shape.
+ */
+int okpz_set_threads(okpz_lattice *lat, uint32_t threads);
 
 /* Copy the parameters the handle was created with. */
 int okpz_get_params(const okpz_lattice *lat, okpz_params *out);

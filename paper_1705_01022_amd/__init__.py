@@ -100,6 +100,7 @@ _SIGS = {
     "okpz_measure": (ctypes.c_int, [_P, ctypes.POINTER(Moments)]),
     "okpz_snapshot": (ctypes.c_int, [_P]),
     "okpz_autocorr": (ctypes.c_int, [_P, ctypes.POINTER(Correlation)]),
+    "okpz_observe": (ctypes.c_int, [_P, ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
     "okpz_get_sites": (ctypes.c_int, [_P, _P]),
     "okpz_get_window": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint32, _P]),
@@ -110,6 +111,7 @@ _SIGS = {
     "okpz_device_words": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "okpz_get_mcs": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     "okpz_get_params": (ctypes.c_int, [_P, ctypes.POINTER(Params)]),
+    "okpz_set_threads": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "okpz_sync": (ctypes.c_int, [_P]),
     "okpz_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "okpz_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
@@ -237,6 +239,10 @@ class Lattice:
     def run(self, n_mcs: int, p: float, q: float):
         _check(load().okpz_run(self._h, n_mcs, p, q), "okpz_run")
 
+    def set_threads(self, threads: int):
+        """Device-step workgroup size (64, 128, 256; 0 = default); results do not change."""
+        _check(load().okpz_set_threads(self._h, threads), "okpz_set_threads")
+
     def sync(self):
         _check(load().okpz_sync(self._h), "okpz_sync")
 
@@ -248,6 +254,21 @@ class Lattice:
                 "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
                 "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
                 "w2": m.w2, "w2_sub": m.w2_sub}
+
+    def observe(self, with_autocorr: bool = True):
+        """Moments and (optionally) C_h from one pass; returns (moments, corr or None)."""
+        m, c = Moments(), Correlation()
+        _check(load().okpz_observe(self._h, ctypes.byref(m), ctypes.byref(c) if with_autocorr else None),
+               "okpz_observe")
+        mo = {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
+              "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
+              "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
+              "w2": m.w2, "w2_sub": m.w2_sub}
+        ac = None
+        if with_autocorr:
+            ac = {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
+                  "s1_s": _to_int(c.s1_s), "c_h": c.c_h}
+        return mo, ac
 
     def snapshot(self):
         _check(load().okpz_snapshot(self._h), "okpz_snapshot")

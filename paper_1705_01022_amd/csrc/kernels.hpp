@@ -1,9 +1,13 @@
 // Device kernels of the octahedron-model simulator (gfx950).
 //
-// Packed lattice: uint32 word (y/4)*(L/4) + x/4 holds a 4x4 block of sites,
-// bit 4*(y%4)+x%4 = sx (slope to the left neighbour is +1), bit
-// 16+4*(y%4)+x%4 = sy (slope to the neighbour at y-1 is +1) - the paper's
-// 2-bit-per-site, 16-sites-per-word coding (Sec. 3.1).
+// Lattice layout in HBM ("block words"): the L x L sites are cut into blocks
+// of 32 x 4 sites; block (bx, by) = (x / 32, y / 4) has index by * (L/32) + bx
+// and owns 8 consecutive uint32 words: words 0..3 hold the sx slope bits of
+// its rows y%4 = 0..3, words 4..7 the sy bits, bit x%32 of each word.  sx = 1
+// means the slope to the left neighbour is +1, sy = 1 the slope to the
+// neighbour at y-1 is +1.  Two bits per site as in the paper's bit-coded
+// lattice (Sec. 3.1), arranged as row bit-planes so that one funnel shift
+// yields a site's two x-slopes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,16 +17,21 @@
 
 namespace okpz {
 
-constexpr uint32_t kFlatWord = 0x5A5A5A5Au;  // h = (x+y) mod 2: slopes +1 on odd sites
+// h = (x+y) mod 2: slopes +1 on odd sites; rows with y even read 1010..,
+// odd rows 0101.., for both bit planes
+constexpr uint32_t kFlatEvenRow = 0xAAAAAAAAu;
+constexpr uint32_t kFlatOddRow = 0x55555555u;
 
 enum : int { kDT = 0, kDB = 1, kDTR = 2 };
 
 // ---------------------------------------------------------------- init
-__global__ void fill_words_kernel(uint32_t *__restrict__ words, uint64_t n, uint32_t value)
+// Flat state: word i of the lattice belongs to row i % 4 of its block, so
+// its parity is that of i.
+__global__ void fill_flat_kernel(uint32_t *__restrict__ words, uint64_t n)
 {
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-        words[i] = value;
+        words[i] = (i & 1u) ? kFlatOddRow : kFlatEvenRow;
 }
 
 // ---------------------------------------------------------------- Philox test
@@ -43,7 +52,9 @@ __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t *__restri
 // (Sec. 3 DTr; Sec. 3.1 application on GPUs).  One workgroup per tile.
 struct StepArgs {
     uint32_t *words;
-    uint32_t lw_mask, lw_log2;  // words per row - 1, log2(words per row)
+    uint32_t nbx_log2;          // log2(blocks per band) = log2(L/32)
+    uint32_t nbx_mask;          // L/32 - 1
+    uint32_t nby_mask;          // L/4 - 1 (bands)
     uint32_t L_mask;            // L - 1
     uint32_t Dx, Dy;            // domain size (sites)
     uint32_t log2Cx, log2Cy;    // cell size (sites), log2
@@ -57,201 +68,394 @@ struct StepArgs {
     uint32_t s_bits;            // site-index bits of the lane draw
     uint32_t F_log2;            // log2 of the lane-draw field width
     uint32_t rounds;            // Cx*Cy single-hit rounds per step
-    uint32_t Wx, Wy, pitch;     // LDS window of the domain + halo, in words
-    uint32_t dep_always, rem_always;  // p == 1 / q == 1 when no acceptance draw is needed
+    uint32_t NWX;               // window width in blocks
+    uint32_t NB;                // window height in bands
+    uint32_t P;                 // LDS sx plane: row pitch in words (odd, > NWX)
+    uint32_t NR;                // window rows (4 NB)
+    uint32_t PY;                // LDS sy plane: column pitch in words (odd, > NR)
+    uint32_t shared_edges;      // Dx < 32: edge blocks may be shared with another domain
+    uint32_t flip_table;        // no acceptance draw: bit k set iff slope pattern k flips
     uint32_t P_hi, P_lo, Q_hi, Q_lo;  // acceptance thresholds on the (A+32)-bit variate
 };
 
-// LDS staging of the domain window: word rows wy0 .. wy0+Wy-1 and word
-// columns wx0 .. wx0+Wx-1 (periodic).  Each wave copies whole rows, so
-// global accesses are contiguous runs of Wx words.
+// Slope pattern of an attempt: bit 0 sx(x,y), bit 1 sx(x+1,y), bit 2 sy(x,y),
+// bit 3 sy(x,y+1).  Local minimum (0,1,0,1) = 0xA, local maximum = 0x5.
+constexpr uint32_t kPatternMin = 0xAu, kPatternMax = 0x5u;
+
+// LDS staging.  The window covers bands by0 .. by0+NB-1 and blocks
+// bx0 .. bx0+NWX-1 (periodic) of the lattice, i.e. the domain plus the column
+// to its right and the row below.  In LDS it becomes two bit planes of
+// NR = 4 NB rows: sx row-major (word row * P + k, so a site's word and the
+// next one are adjacent) and sy column-major (word sy_base + k * PY + row, so
+// rows y and y+1 are adjacent); P > NWX and PY > NR are odd, the padding is
+// never written back.  Each wave copies whole bands: contiguous runs of 8 NWX words.
+// When the domain is narrower than a block (Dx < 32) the first and last block
+// of a band may also belong to another domain of the same set; their bits
+// are then written back as an XOR with what was loaded (the two domains
+// change disjoint bits), using the copy kept in `orig`.
 template <bool LOAD>
-__device__ __forceinline__ void copy_window(const StepArgs &A, uint32_t *lds, uint32_t wx0, uint32_t wy0)
+__device__ __forceinline__ void copy_window(const StepArgs &A, uint32_t *lds, uint32_t *orig, uint32_t bx0,
+                                            uint32_t by0)
 {
     const uint32_t nwaves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    for (uint32_t r = wave; r < A.Wy; r += nwaves) {
-        uint32_t *row = A.words + (static_cast<uint64_t>((wy0 + r) & A.lw_mask) << A.lw_log2);
-        for (uint32_t c = lane; c < A.Wx; c += 64) {
-            const uint32_t gx = (wx0 + c) & A.lw_mask;
-            if (LOAD)
-                lds[r * A.pitch + c] = row[gx];
-            else
-                row[gx] = lds[r * A.pitch + c];
+    const uint32_t sy_base = A.NR * A.P;
+    for (uint32_t b = wave; b < A.NB; b += nwaves) {
+        const uint64_t band = static_cast<uint64_t>((by0 + b) & A.nby_mask) << A.nbx_log2;
+        for (uint32_t t = lane; t < 8u * A.NWX; t += 64) {
+            const uint32_t k = t >> 3, wib = t & 7u, row = 4u * b + (wib & 3u);
+            const uint64_t g = ((band + ((bx0 + k) & A.nbx_mask)) << 3) + wib;
+            const uint32_t li = wib < 4u ? row * A.P + k : sy_base + k * A.PY + row;
+            const bool edge = A.shared_edges && (k == 0 || k == A.NWX - 1);
+            const uint32_t oi = (b * 2u + (k == 0 ? 0u : 1u)) * 8u + wib;
+            if (LOAD) {
+                const uint32_t v = A.words[g];
+                lds[li] = v;
+                if (edge) orig[oi] = v;
+            } else {
+                if (edge)
+                    atomicXor(&A.words[g], lds[li] ^ orig[oi]);
+                else
+                    A.words[g] = lds[li];
+            }
         }
     }
 }
 
-// One update attempt at LDS site (lx, ly) (Sec. 2.1 rule): read sx, sy of
-// the site, sx of (lx+1, ly) and sy of (lx, ly+1); a local minimum
-// (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed; both
-// flip the same four bits.  Flips are LDS atomic XORs because attempts of
-// neighbouring cells may share a word (never a bit).
-template <bool ACCEPT>
-__device__ __forceinline__ void do_attempt(const StepArgs &A, uint32_t *lds, uint32_t lx, uint32_t ly,
-                                           uint32_t upre, uint32_t rho, uint32_t cell, uint32_t tile)
+// One cell's attempt in one round, decoded from its lane draw.
+struct Draw {
+    uint32_t ix;    // byte offset of the site's sx-plane word: 4 (row * P + column / 32)
+    uint32_t iy;    // byte offset of its sy-plane word: 4 (sy_base + (column / 32) * PY + row)
+    uint32_t sh;    // site bit in those words (column % 32)
+    uint32_t upre;  // acceptance prefix (top F - s_bits bits of the field)
+    uint32_t rlo;   // low 32 bits of the acceptance variate (drawn only on a prefix tie)
+    uint32_t pos;   // domain-local u | v << 16
+    uint32_t rim;   // bit 0: right column of its cell, bit 1: bottom row (DB)
+};
+
+// Consumes the next F-bit field of a cell's lane-draw stream for round rho
+// (rounds must be drawn in increasing order): field f = rho mod (128/F) of
+// Philox block (rho / (128/F), cell, tile, 4*MCS+step), lowest bits first.
+__device__ __forceinline__ uint32_t next_field(const StepArgs &A, uint32_t (&rw)[4], uint32_t rho, uint32_t cell,
+                                               uint32_t tile)
 {
-    const uint32_t wi = (ly >> 2) * A.pitch + (lx >> 2);
-    const uint32_t bx = lx & 3u, by = ly & 3u;
-    const uint32_t sxb = 4u * by + bx;
-    const uint32_t w = lds[wi];
-    const uint32_t wr = (bx == 3u) ? lds[wi + 1] : w;
-    const uint32_t wd = (by == 3u) ? lds[wi + A.pitch] : w;
-    const uint32_t a = (w >> sxb) & 1u;
-    const uint32_t c = (w >> (16u + sxb)) & 1u;
-    const uint32_t b = (wr >> (4u * by + ((bx + 1u) & 3u))) & 1u;
-    const uint32_t d = (wd >> (16u + 4u * ((by + 1u) & 3u) + bx)) & 1u;
-    const uint32_t pat = a | (b << 1) | (c << 2) | (d << 3);
-    const bool is_min = pat == 0xAu;  // a=0 b=1 c=0 d=1
-    const bool is_max = pat == 0x5u;  // a=1 b=0 c=1 d=0
-    bool flip;
+    const uint32_t per_word_mask = (32u >> A.F_log2) - 1u;
+    const uint32_t per_call_mask = (128u >> A.F_log2) - 1u;
+    const uint32_t F = 1u << A.F_log2;
+    if ((rho & per_call_mask) == 0u) {
+        const u32x4 r = philox4x32_10(A.key0, A.key1, rho >> (7u - A.F_log2), cell, tile, A.c3);
+        rw[0] = r.x; rw[1] = r.y; rw[2] = r.z; rw[3] = r.w;
+    }
+    // field f of the current word: bits F*f .. F*f+F-1 (the offset is uniform;
+    // the bit-field extract takes its width mod 32, so F = 32 is the word)
+    const uint32_t field = F == 32u ? rw[0] : __builtin_amdgcn_ubfe(rw[0], (rho & per_word_mask) << A.F_log2, F);
+    if (((rho + 1u) & per_word_mask) == 0u) {  // word used up: move to the next one
+        rw[0] = rw[1];
+        rw[1] = rw[2];
+        rw[2] = rw[3];
+    }
+    return field;
+}
+
+// Block draw of round rho: 16-bit field rho mod 8 of Philox block
+// (rho / 8, 0xFFFFFFFF, tile, 4*MCS+step): bits 0-1 the block-level domain
+// set (DT, DTr), bits 2-7 and 8-13 the shift of the cell grid (DB, DTr).
+struct BlockDraw {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ uint32_t next_block_field(const StepArgs &A, BlockDraw &b, uint32_t rho, uint32_t tile)
+{
+    if ((rho & 7u) == 0u) {
+        const u32x4 r = philox4x32_10(A.key0, A.key1, rho >> 3, 0xFFFFFFFFu, tile, A.c3);
+        b.w0 = r.x; b.w1 = r.y; b.w2 = r.z; b.w3 = r.w;
+    }
+    const uint32_t f16 = b.w0 & 0xFFFFu;
+    if (rho & 1u) {
+        b.w0 = b.w1; b.w1 = b.w2; b.w2 = b.w3;
+    } else {
+        b.w0 >>= 16;
+    }
+    return f16;
+}
+
+// Site of a cell's attempt from its field (low s_bits) and the round's block
+// field f16.  base_u, base_v: the cell's corner in the domain; offx, offy:
+// the domain's offset inside its first block / band.
+template <int SCHEME, bool ACCEPT>
+__device__ __forceinline__ Draw decode(const StepArgs &A, uint32_t field, uint32_t f16, uint32_t base_u,
+                                       uint32_t base_v, uint32_t offx, uint32_t offy)
+{
+    const uint32_t idx = field & ((1u << A.s_bits) - 1u);
+    uint32_t du, dv, u, v;
+    if (SCHEME == kDB) {
+        du = idx & ((1u << A.log2Cx) - 1u);
+        dv = idx >> A.log2Cx;
+    } else {
+        const uint32_t hw = A.log2Cx - 1u;  // quadrant of the cell chosen by bits 0-1
+        du = ((f16 & 1u) << hw) + (idx & ((1u << hw) - 1u));
+        dv = (((f16 >> 1) & 1u) << (A.log2Cy - 1u)) + (idx >> hw);
+    }
+    if (SCHEME == kDT) {
+        u = base_u + du;  // cell grid fixed: never wraps
+        v = base_v + dv;
+    } else {
+        const uint32_t shx = (f16 >> 2) & ((1u << A.log2Cx) - 1u), shy = (f16 >> 8) & ((1u << A.log2Cy) - 1u);
+        u = (shx + base_u + du) & (A.Dx - 1u);
+        v = (shy + base_v + dv) & (A.Dy - 1u);
+    }
+    const uint32_t lx = u + offx, ly = v + offy;
+    Draw d;
+    d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
+    d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
+    d.sh = lx & 31u;
+    d.upre = ACCEPT ? field >> A.s_bits : 0u;
+    d.rlo = 0u;
+    d.pos = SCHEME == kDB ? u | (v << 16) : 0u;
+    d.rim = SCHEME == kDB ? ((du == (1u << A.log2Cx) - 1u) ? 1u : 0u) | ((dv == (1u << A.log2Cy) - 1u) ? 2u : 0u)
+                          : 0u;
+    return d;
+}
+
+// Low word of the acceptance variate, needed only when the prefix equals the
+// prefix of P or Q (probability about 2^(1-A)): word 0 of Philox block
+// (rho, cell | 0x80000000, tile, 4*MCS+step).
+template <bool ACCEPT>
+__device__ __forceinline__ void draw_tie(const StepArgs &A, Draw &d, uint32_t rho, uint32_t cell, uint32_t tile)
+{
+    if (ACCEPT && (d.upre == A.P_hi || d.upre == A.Q_hi))
+        d.rlo = philox4x32_10(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
+}
+
+// One update attempt (Sec. 2.1 rule) at the site of d.  With the window as
+// bit planes, a = sx(x,y) and b = sx(x+1,y) are two adjacent bits of the sx
+// row (a funnel shift over the word and the next one), c = sy(x,y) and
+// d = sy(x,y+1) the same bit of two consecutive sy rows.  A local minimum
+// (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed; both flip
+// the same four bits with LDS atomic XORs (zero masks when nothing flips, or
+// when `enable` is false), because attempts of different cells may share a
+// word (never a bit).  All decisions are bitwise; the only branch guards the
+// rare flip of sx(x+1) in the next word (x at bit 31).
+template <bool ACCEPT>
+__device__ __forceinline__ void attempt(const StepArgs &A, uint32_t *lds, const Draw &d, bool enable = true)
+{
+    char *base = reinterpret_cast<char *>(lds);
+    uint32_t *px = reinterpret_cast<uint32_t *>(base + d.ix);
+    uint32_t *py = reinterpret_cast<uint32_t *>(base + d.iy);
+    const uint32_t w0 = px[0], w1 = px[1];
+    const uint32_t y0 = py[0], y1 = py[1];
+    const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, d.sh) & 3u;
+    const uint32_t key = ab | (__builtin_amdgcn_ubfe(y0, d.sh, 1) << 2) | (__builtin_amdgcn_ubfe(y1, d.sh, 1) << 3);
+    uint32_t flip;
     if (ACCEPT) {
-        // U = (upre << 32) | r compared with P (deposition) or Q (removal);
-        // r is drawn only when the prefix ties with the threshold's prefix.
+        // U = (upre << 32) | rlo below P (deposition) or Q (removal)
+        const bool is_min = key == kPatternMin;
         const uint32_t thr_hi = is_min ? A.P_hi : A.Q_hi;
         const uint32_t thr_lo = is_min ? A.P_lo : A.Q_lo;
-        flip = (is_min || is_max) && upre < thr_hi;
-        if ((is_min || is_max) && upre == thr_hi) {
-            const u32x4 r = philox4x32_10(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3);
-            flip = r.x < thr_lo;
-        }
+        const uint32_t below = (d.upre < thr_hi ? 1u : 0u) | ((d.upre == thr_hi ? 1u : 0u) & (d.rlo < thr_lo ? 1u : 0u));
+        flip = (((1u << kPatternMin) | (1u << kPatternMax)) >> key) & below;
     } else {
-        flip = (is_min && A.dep_always) || (is_max && A.rem_always);
+        flip = A.flip_table >> key;
     }
-    if (flip) {
-        uint32_t m0 = (1u << sxb) | (1u << (16u + sxb));
-        if (bx != 3u)
-            m0 |= 1u << (sxb + 1u);
-        else
-            atomicXor(&lds[wi + 1], 1u << (4u * by));
-        if (by != 3u)
-            m0 |= 1u << (16u + sxb + 4u);
-        else
-            atomicXor(&lds[wi + A.pitch], 1u << (16u + bx));
-        atomicXor(&lds[wi], m0);
+    flip &= enable ? 1u : 0u;
+    const uint32_t m = (flip & 1u) << d.sh;
+    atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
+    atomicXor(&py[0], m);             // sy(x, y)
+    atomicXor(&py[1], m);             // sy(x, y+1)
+    if (m >> 31) atomicXor(&px[1], 1u);  // sx(x+1) in the next word
+}
+
+// A cell's published-site slot: cell c of thread c / CPT is stored at
+// (c % CPT) * NT + c / CPT, so the lanes of one instruction touch
+// consecutive words (no bank conflicts); nb_r, nb_d are the slots of the
+// cells to the right and below.
+struct CellGeom {
+    uint32_t base;  // cell corner in the domain: base_u | base_v << 16
+    uint32_t nb;    // published-site slots of the cells to the right (low 16 bits) and below
+};
+
+// DB: draw round rho+1 for every cell of the thread into nxt and publish
+// the sites (buffer (rho+1) & 1), then run round rho whose draws are in cur:
+// the attempts that do not depend on phase order at once, the deferred ones
+// after the barrier in phase order.
+template <bool ACCEPT, int CPT>
+__device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint32_t *cpos, uint32_t *flags,
+                                         const CellGeom (&g)[CPT], uint32_t (&rw)[CPT][4], BlockDraw &bd,
+                                         Draw (&cur)[CPT], Draw (&nxt)[CPT], uint32_t rho, uint32_t tile,
+                                         uint32_t offx, uint32_t offy, bool active_lane)
+{
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    if (rho + 1u < A.rounds) {
+        const uint32_t f16 = next_block_field(A, bd, rho + 1u, tile);
+        const uint32_t nbuf = ((rho + 1u) & 1u) * A.ncell;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const uint32_t field = next_field(A, rw[j], rho + 1u, tid * CPT + j, tile);
+            nxt[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
+            if (CPT > 1 || active_lane) cpos[nbuf + j * NT + tid] = nxt[j].pos;
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, nxt[j], rho + 1u, tid * CPT + j, tile);
     }
+    // A rim attempt waits if the neighbouring cell's attempt sits on the site
+    // to its right (right column / corner) or below it (bottom row / corner).
+    // A target one past the domain edge is never a published site.
+    const uint32_t buf = (rho & 1u) * A.ncell;
+    bool def[CPT];
+    bool any1 = false, any2 = false;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const uint32_t pr = cpos[buf + (g[j].nb & 0xFFFFu)], pd = cpos[buf + (g[j].nb >> 16)];
+        const uint32_t want_r = (cur[j].rim & 1u) ? cur[j].pos + 1u : 0xFFFFFFFFu;
+        const uint32_t want_d = (cur[j].rim & 2u) ? cur[j].pos + 0x10000u : 0xFFFFFFFFu;
+        def[j] = (CPT > 1 || active_lane) && (pr == want_r || pd == want_d);
+        any1 |= def[j] && cur[j].rim != 3u;
+        any2 |= def[j] && cur[j].rim == 3u;
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, cur[j], !def[j] && (CPT > 1 || active_lane));
+    const uint64_t b1 = __ballot(any1), b2 = __ballot(any2);
+    if ((tid & 63u) == 0u && (b1 | b2)) atomicOr(&flags[rho % 3u], (b1 ? 1u : 0u) | (b2 ? 2u : 0u));
+    if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
+    __syncthreads();
+    const uint32_t f = flags[rho % 3u];
+    if (f & 1u) {  // deferred edge attempts
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (def[j] && cur[j].rim != 3u) attempt<ACCEPT>(A, lds, cur[j]);
+        __syncthreads();
+    }
+    if (f & 2u) {  // deferred corner attempts
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (def[j] && cur[j].rim == 3u) attempt<ACCEPT>(A, lds, cur[j]);
+        __syncthreads();
+    }
+}
+
+// LDS words of one device-step workgroup (see step_kernel).
+__host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint32_t NWX, uint32_t PY, uint32_t NB,
+                                                   uint32_t shared_edges, uint32_t ncell, bool db)
+{
+    return NR * P + (NWX + 1u) * PY + (shared_edges ? 16u * NB : 0u) + (db ? 2u * ncell + 4u : 0u);
 }
 
 // One device step.  Workgroup = one tile; its active domain (sub-tile set
 // (set_a, set_b)) is staged with its +x column and +y row in LDS, swept by
-// Cx*Cy single-hit rounds (each cell gets exactly one attempt per round),
-// and written back.  Same-set domains never share a word when the domain
-// is at least 4 sites wide, so whole-word write-back is race-free.
+// Cx*Cy single-hit rounds (every cell gets exactly one attempt per round,
+// Sec. 3.1) and written back.  Same-set domains of at least 32 sites never
+// share a block, so their write-back is plain; narrower ones XOR their
+// changes into the two edge blocks of each band.
 //
-// Lane draws: cell c takes F-bit fields of the Philox block
-// (round / (128/F), c, tile, 4*MCS+step), lowest bits first; the low
-// s_bits pick the site (in the chosen quadrant for DT/DTr, anywhere in the
-// cell for DB) and the rest is the acceptance prefix.  Block draws: 16-bit
-// fields of (round/8, 0xFFFFFFFF, tile, 4*MCS+step): bits 0-1 quadrant,
-// 2-7 and 8-13 the cell-grid shift.
+// DT / DTr: the attempts of one round never touch each other, so a round is
+// one pass.  DB (delayed borders: bulk attempts first, then those on the
+// right column or bottom row of their cell, the corner last): only a rim
+// attempt whose right or lower neighbour site holds an earlier-phase attempt
+// of the neighbouring cell depends on the order, so every other attempt of
+// the round runs in the first pass and the few dependent ones in one or two
+// later passes.  All attempts of the first pass are pairwise non-adjacent
+// and commute with the deferred ones they precede in phase order, so the
+// result equals bulk -> edges -> corners exactly.  Attempt sites depend only
+// on the random stream, so each cell publishes its next round's site one
+// round ahead (double-buffered in LDS) and the check needs no extra barrier.
 template <int SCHEME, bool ACCEPT, int CPT>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint32_t smem[];
+    uint32_t *lds = smem;                                              // sx plane, then sy plane
+    uint32_t *orig = smem + A.NR * A.P + (A.NWX + 1u) * A.PY;          // edge blocks as loaded
+    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // DB: 2 x ncell published sites
+    uint32_t *flags = cpos + 2 * A.ncell;                              // DB: 3 round flags
+
     const uint32_t tile = blockIdx.x;
     const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
     const uint32_t X0 = (A.ox + 2u * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
     const uint32_t Y0 = (A.oy + 2u * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
-    const uint32_t offx = X0 & 3u, offy = Y0 & 3u;
+    const uint32_t offx = X0 & 31u, offy = Y0 & 3u;
 
-    copy_window<true>(A, lds, X0 >> 2, Y0 >> 2);
+    copy_window<true>(A, lds, orig, X0 >> 5, Y0 >> 2);
 
-    const uint32_t NT = blockDim.x;
-    const uint32_t Cx = 1u << A.log2Cx, Cy = 1u << A.log2Cy;
-    const uint32_t F = 1u << A.F_log2;
-    const uint32_t per_word_mask = (32u >> A.F_log2) - 1u;    // fields per word - 1
-    const uint32_t per_call_mask = (128u >> A.F_log2) - 1u;   // fields per call - 1
-    const uint32_t fmask = F == 32u ? 0xFFFFFFFFu : ((1u << F) - 1u);
-    const uint32_t smask = (1u << A.s_bits) - 1u;
-    const uint32_t hw_log2 = A.log2Cx - 1u;                   // DT quadrant width, log2
-
-    uint32_t cell[CPT], base_u[CPT], base_v[CPT];
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    const uint32_t ncx_mask = (1u << A.log2ncx) - 1u;
+    const uint32_t ncy_mask = (A.ncell >> A.log2ncx) - 1u;
+    // a cell's published-site slot: cell c of thread c / CPT is stored at
+    // (c % CPT) * NT + c / CPT, so the lanes of one instruction touch
+    // consecutive words (no LDS bank conflicts)
+    auto slot_of = [&](uint32_t c) { return (c % CPT) * NT + c / CPT; };
+    CellGeom g[CPT];
     uint32_t rw[CPT][4];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        cell[j] = threadIdx.x + j * NT;
-        base_u[j] = (cell[j] & ((1u << A.log2ncx) - 1u)) << A.log2Cx;
-        base_v[j] = (cell[j] >> A.log2ncx) << A.log2Cy;
+        // a thread's cells are horizontal neighbours, so the lanes of one
+        // instruction hit different LDS words
+        const uint32_t cell = tid * CPT + j;
+        const uint32_t cx = cell & ncx_mask, cy = (cell >> A.log2ncx) & ncy_mask;
+        g[j].base = (cx << A.log2Cx) | ((cy << A.log2Cy) << 16);
+        g[j].nb = slot_of((cy << A.log2ncx) | ((cx + 1u) & ncx_mask)) |
+                  (slot_of((((cy + 1u) & ncy_mask) << A.log2ncx) | cx) << 16);
+        rw[j][0] = rw[j][1] = rw[j][2] = rw[j][3] = 0u;
     }
-    uint32_t bw0 = 0, bw1 = 0, bw2 = 0, bw3 = 0;
-    __syncthreads();
+    const bool active_lane = tid * CPT < A.ncell;  // CPT = 1 workgroups may have idle lanes
+    BlockDraw bd = {0u, 0u, 0u, 0u};
 
-    for (uint32_t rho = 0; rho < A.rounds; ++rho) {
-        if ((rho & 7u) == 0u) {
-            const u32x4 r = philox4x32_10(A.key0, A.key1, rho >> 3, 0xFFFFFFFFu, tile, A.c3);
-            bw0 = r.x; bw1 = r.y; bw2 = r.z; bw3 = r.w;
-        }
-        const uint32_t f16 = bw0 & 0xFFFFu;
-        if (rho & 1u) {
-            bw0 = bw1; bw1 = bw2; bw2 = bw3;
-        } else {
-            bw0 >>= 16;
-        }
-        const uint32_t sigma = f16 & 3u;
-        const uint32_t bx = SCHEME == kDT ? 0u : ((f16 >> 2) & (Cx - 1u));
-        const uint32_t by = SCHEME == kDT ? 0u : ((f16 >> 8) & (Cy - 1u));
-
-        uint32_t lx[CPT], ly[CPT], upre[CPT], phase[CPT];
-        const bool refill = (rho & per_call_mask) == 0u;
-        const bool rotate = ((rho + 1u) & per_word_mask) == 0u;
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            if (refill) {
-                const u32x4 r = philox4x32_10(A.key0, A.key1, rho >> (7u - A.F_log2), cell[j], tile, A.c3);
-                rw[j][0] = r.x; rw[j][1] = r.y; rw[j][2] = r.z; rw[j][3] = r.w;
-            }
-            const uint32_t field = rw[j][0] & fmask;
-            if (rotate) {
-                rw[j][0] = rw[j][1]; rw[j][1] = rw[j][2]; rw[j][2] = rw[j][3];
-            } else {
-                rw[j][0] >>= (F & 31u);  // F < 32 here: rotation handles F = 32
-            }
-            const uint32_t idx = field & smask;
-            uint32_t du, dv;
-            if (SCHEME == kDB) {
-                du = idx & (Cx - 1u);
-                dv = idx >> A.log2Cx;
-            } else {
-                du = ((sigma & 1u) << hw_log2) + (idx & ((1u << hw_log2) - 1u));
-                dv = ((sigma >> 1) << (A.log2Cy - 1u)) + (idx >> hw_log2);
-            }
-            const uint32_t u = (bx + base_u[j] + du) & (A.Dx - 1u);
-            const uint32_t v = (by + base_v[j] + dv) & (A.Dy - 1u);
-            lx[j] = u + offx;
-            ly[j] = v + offy;
-            upre[j] = ACCEPT ? (field >> A.s_bits) : 0u;
-            phase[j] = SCHEME == kDB ? (uint32_t)(du == Cx - 1u) + (uint32_t)(dv == Cy - 1u) : 0u;
-        }
-        constexpr int NPH = SCHEME == kDB ? 3 : 1;
-#pragma unroll
-        for (int ph = 0; ph < NPH; ++ph) {
+    if (SCHEME != kDB) {
+        __syncthreads();
+        for (uint32_t rho = 0; rho < A.rounds; ++rho) {
+            const uint32_t f16 = next_block_field(A, bd, rho, tile);
+            Draw d[CPT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                if (cell[j] < A.ncell && phase[j] == (uint32_t)ph)
-                    do_attempt<ACCEPT>(A, lds, lx[j], ly[j], upre[j], rho, cell[j], tile);
+                const uint32_t field = next_field(A, rw[j], rho, tid * CPT + j, tile);
+                d[j] = decode<SCHEME, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
             }
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, d[j], rho, tid * CPT + j, tile);
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, d[j], CPT > 1 || active_lane);
             __syncthreads();
         }
+    } else {
+        Draw da[CPT], db[CPT];
+        const uint32_t f16 = next_block_field(A, bd, 0u, tile);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const uint32_t field = next_field(A, rw[j], 0u, tid * CPT + j, tile);
+            da[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
+            if (CPT > 1 || active_lane) cpos[j * NT + tid] = da[j].pos;
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, da[j], 0u, tid * CPT + j, tile);
+        if (tid < 3) flags[tid] = 0u;
+        __syncthreads();
+        // Cx*Cy rounds, an even number: alternate the two draw buffers
+        for (uint32_t rho = 0; rho < A.rounds; rho += 2) {
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, da, db, rho, tile, offx, offy, active_lane);
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, db, da, rho + 1u, tile, offx, offy, active_lane);
+        }
     }
-    copy_window<false>(A, lds, X0 >> 2, Y0 >> 2);
+    copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
 }
 
 // ---------------------------------------------------------------- measurement
 // Heights (gauge h(0,0) = 0): h(0,y) = sum_{y'=1..y} (2 sy[0,y'] - 1);
 // h(x,y) = h(0,y) + sum_{x'=1..x} (2 sx[x',y] - 1).
 
-// Column-0 anchors h(0,y), one workgroup of 1024 threads.
+// Column-0 anchors h(0,y): one workgroup; each thread owns a run of bands,
+// reads the sy words of block 0 of each band, and a block scan joins the runs.
 __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
-                                                       uint32_t lw_log2, int32_t *__restrict__ h0)
+                                                       uint32_t nbx_log2, int32_t *__restrict__ h0)
 {
     __shared__ int32_t part[1024];
     const uint32_t T = blockDim.x, tid = threadIdx.x;
-    const uint32_t chunk = (L + T - 1) / T;
-    const uint32_t y0 = tid * chunk;
+    const uint32_t nband = L >> 2;
+    const uint32_t chunk = (nband + T - 1) / T;
+    const uint32_t b0 = tid * chunk;
     int32_t local = 0;
-    for (uint32_t y = y0; y < y0 + chunk && y < L; ++y) {
-        if (y == 0) continue;
-        const uint32_t w = words[static_cast<uint64_t>(y >> 2) << lw_log2];
-        local += 2 * (int32_t)((w >> (16u + 4u * (y & 3u))) & 1u) - 1;
+    for (uint32_t k = 0; k < chunk; ++k) {
+        const uint32_t b = b0 + k;
+        if (b >= nband) break;
+        const uint4 sy = *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b) << nbx_log2) << 3) + 4);
+        const int32_t bits = (int32_t)((sy.x & 1u) + (sy.y & 1u) + (sy.z & 1u) + (sy.w & 1u));
+        local += b == 0 ? 2 * (bits - (int32_t)(sy.x & 1u)) - 3 : 2 * bits - 4;  // row 0 has no step
     }
     part[tid] = local;
     __syncthreads();
@@ -261,148 +465,179 @@ __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restric
         part[tid] += v;
         __syncthreads();
     }
-    int32_t h = part[tid] - local;  // exclusive prefix
-    for (uint32_t y = y0; y < y0 + chunk && y < L; ++y) {
-        if (y > 0) {
-            const uint32_t w = words[static_cast<uint64_t>(y >> 2) << lw_log2];
-            h += 2 * (int32_t)((w >> (16u + 4u * (y & 3u))) & 1u) - 1;
+    int32_t h = part[tid] - local;  // exclusive prefix: h(0, 4 b0 - 1)
+    for (uint32_t k = 0; k < chunk; ++k) {
+        const uint32_t b = b0 + k;
+        if (b >= nband) break;
+        const uint4 sy = *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b) << nbx_log2) << 3) + 4);
+        const uint32_t r4[4] = {sy.x, sy.y, sy.z, sy.w};
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t y = 4 * b + r;
+            if (y > 0) h += 2 * (int32_t)(r4[r] & 1u) - 1;
+            h0[y] = h;
         }
-        h0[y] = h;
     }
 }
 
-// Wave-level inclusive scan of 64-bit values (wave64).
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
+__device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t v, int32_t &total)
 {
     const uint32_t lane = threadIdx.x & 63u;
+    int32_t inc = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t o = __shfl_up(v, off, 64);
-        if (lane >= (uint32_t)off) v += o;
+        const int32_t o = __shfl_up(inc, off, 64);
+        if (lane >= (uint32_t)off) inc += o;
     }
+    total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// Exclusive block scan of packed 64-bit values (4 x 16-bit lanes, no
-// carries between fields by construction); returns the exclusive prefix and
-// the block total.
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *wave_tot, uint64_t &total)
+constexpr int kMomentFields = 5;  // S1_even, S1_odd, S2_even, S2_odd, S_ts
+
+// Row-nibble table: for 4 consecutive sites of a row (x % 4 = 0..3) with
+// steps e_i = 2 b_i - 1 (e_0 = 0 for the row's first site, entries 16..31)
+// and prefixes p_i = e_0 + .. + e_i: bits 0-7 p0+p2, 8-15 p1+p3 (signed),
+// 16-20 p0^2+p2^2, 21-25 p1^2+p3^2, 26-29 p3+4.  Pair table: sum_i pt_i ps_i
+// for two nibbles of the same sites (index first*256 + nt*16 + ns).
+__device__ __forceinline__ void row_prefixes(uint32_t nib, uint32_t first, int32_t (&p)[4])
 {
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint64_t inc = wave_incl_scan(v);
-    if (lane == 63u) wave_tot[wave] = inc;
-    __syncthreads();
-    uint64_t before = 0, all = 0;
-    for (uint32_t i = 0; i < nw; ++i) {
-        const uint64_t t = wave_tot[i];
-        if (i < wave) before += t;
-        all += t;
+    int32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!(i == 0 && first)) acc += 2 * (int32_t)((nib >> i) & 1u) - 1;
+        p[i] = acc;
     }
-    __syncthreads();
-    total = all;
-    return before + inc - v;
+}
+
+template <bool CROSS>
+__device__ void build_tables(uint32_t *lut, int32_t *pair)
+{
+    for (uint32_t i = threadIdx.x; i < 32; i += blockDim.x) {
+        int32_t p[4];
+        row_prefixes(i & 15u, i >> 4, p);
+        lut[i] = (uint32_t)(uint8_t)(int8_t)(p[0] + p[2]) | ((uint32_t)(uint8_t)(int8_t)(p[1] + p[3]) << 8) |
+                 ((uint32_t)(p[0] * p[0] + p[2] * p[2]) << 16) | ((uint32_t)(p[1] * p[1] + p[3] * p[3]) << 21) |
+                 ((uint32_t)(p[3] + 4) << 26);
+    }
+    if (CROSS)
+        for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) {
+            int32_t pt[4], ps[4];
+            row_prefixes((i >> 4) & 15u, i >> 8, pt);
+            row_prefixes(i & 15u, i >> 8, ps);
+            pair[i] = pt[0] * ps[0] + pt[1] * ps[1] + pt[2] * ps[2] + pt[3] * ps[3];
+        }
 }
 
 constexpr int kMeasureThreads = 256;
-constexpr int kMomentFields = 5;  // S1_even, S1_odd, S2_even, S2_odd, S_ts
 
-// Per word-row partial moments.  One workgroup per word row (4 site rows);
-// the words of the row are streamed in chunks of 256 with a block scan of
-// the per-word height increments of the 4 rows (packed in 16-bit fields,
-// biased by +4 so fields stay non-negative).  With a snapshot, the same is
-// done for the snapshot words and sum h_t h_s is accumulated.
+// Per-band partial moments.  One wave per band (4 site rows); lane l handles
+// block l of each chunk of 64 blocks (32 sites of each of the 4 rows).
+// Within its block a lane accumulates sums of heights relative to the
+// block's start, a wave scan gives the block offsets, and the relative sums
+// are shifted to absolute heights: with A the height before the block and q
+// the relative heights, sum h = n A + sum q and sum h^2 = n A^2 + 2 A sum q +
+// sum q^2.  With a snapshot (CROSS), sum h_t h_s is accumulated the same way.
 template <bool CROSS>
 __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *__restrict__ words,
                                                                const int32_t *__restrict__ h0,
                                                                const uint32_t *__restrict__ snap,
                                                                const int32_t *__restrict__ h0s, uint32_t L,
-                                                               uint32_t lw_log2, int64_t *__restrict__ partial)
+                                                               uint32_t nbx_log2, int64_t *__restrict__ partial)
 {
-    __shared__ uint64_t wave_tot[kMeasureThreads / 64];
-    __shared__ int64_t red[kMomentFields][kMeasureThreads];
-    const uint32_t y4 = blockIdx.x, tid = threadIdx.x;
-    const uint32_t lw = 1u << lw_log2;
-    const uint64_t row_base = static_cast<uint64_t>(y4) << lw_log2;
-    int32_t carry[4], carry_s[4], anchor[4], anchor_s[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        carry[r] = 0;
-        carry_s[r] = 0;
-        anchor[r] = h0[4 * y4 + r];
-        anchor_s[r] = CROSS ? h0s[4 * y4 + r] : 0;
-    }
-    int64_t s1e = 0, s1o = 0, s2e = 0, s2o = 0, sts = 0;
-    for (uint32_t base = 0; base < lw; base += kMeasureThreads) {
-        const uint32_t wx = base + tid;
-        const bool active = wx < lw;
-        const uint32_t w = active ? words[row_base + wx] : 0u;
-        const uint32_t ws = (CROSS && active) ? snap[row_base + wx] : 0u;
-        // per-row increments over the word; site x = 0 contributes no step
-        uint64_t packed = 0, packed_s = 0;
-        int32_t inc[4], inc_s[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            uint32_t nib = (w >> (4 * r)) & 0xFu, nib_s = (ws >> (4 * r)) & 0xFu;
-            int32_t steps = 4, steps_s = 4;
-            if (wx == 0) {
-                nib &= 0xEu;
-                nib_s &= 0xEu;
-                steps = 3;
-                steps_s = 3;
-            }
-            inc[r] = 2 * __popc(nib) - steps;
-            inc_s[r] = 2 * __popc(nib_s) - steps_s;
-            if (active) {  // inactive threads sit after every active one and add nothing
-                packed |= static_cast<uint64_t>(inc[r] + 4) << (16 * r);
-                packed_s |= static_cast<uint64_t>(inc_s[r] + 4) << (16 * r);
-            }
-        }
-        uint64_t tot, tot_s = 0;
-        const uint64_t ex = block_excl_scan(packed, wave_tot, tot);
-        uint64_t ex_s = 0;
-        if (CROSS) ex_s = block_excl_scan(packed_s, wave_tot, tot_s);
-        const int32_t nact = (int32_t)min((uint32_t)kMeasureThreads, lw - base);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t pin = carry[r] + (int32_t)((ex >> (16 * r)) & 0xFFFFu) - 4 * (int32_t)tid;
-            const int32_t pin_s = CROSS ? carry_s[r] + (int32_t)((ex_s >> (16 * r)) & 0xFFFFu) - 4 * (int32_t)tid : 0;
-            carry[r] += (int32_t)((tot >> (16 * r)) & 0xFFFFu) - 4 * nact;
-            if (CROSS) carry_s[r] += (int32_t)((tot_s >> (16 * r)) & 0xFFFFu) - 4 * nact;
-            if (!active) continue;
-            const uint32_t y = 4 * y4 + r;
-            int32_t h = anchor[r] + pin, hs = anchor_s[r] + pin_s;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t x = 4 * wx + i;
-                if (x != 0) {
-                    h += 2 * (int32_t)((w >> (4 * r + i)) & 1u) - 1;
-                    if (CROSS) hs += 2 * (int32_t)((ws >> (4 * r + i)) & 1u) - 1;
-                }
-                const int64_t hv = h;
-                if (((x + y) & 1u) == 0u) {
-                    s1e += hv;
-                    s2e += hv * hv;
-                } else {
-                    s1o += hv;
-                    s2o += hv * hv;
-                }
-                if (CROSS) sts += hv * (int64_t)hs;
-            }
-        }
-    }
-    red[0][tid] = s1e;
-    red[1][tid] = s1o;
-    red[2][tid] = s2e;
-    red[3][tid] = s2o;
-    red[4][tid] = sts;
+    __shared__ uint32_t lut[32];
+    __shared__ int32_t pair[CROSS ? 512 : 1];
+    build_tables<CROSS>(lut, pair);
     __syncthreads();
-    for (uint32_t off = kMeasureThreads / 2; off > 0; off >>= 1) {
-        if (tid < off)
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t band = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
+    if (band >= (L >> 2)) return;
+    const uint32_t nbx = 1u << nbx_log2;
+    const uint64_t band_base = (static_cast<uint64_t>(band) << nbx_log2) << 3;
+    int32_t carry[4] = {0, 0, 0, 0}, carry_s[4] = {0, 0, 0, 0};
+    int64_t s1e = 0, s1o = 0, s2e = 0, s2o = 0, sts = 0;
+    for (uint32_t base = 0; base < nbx; base += 64) {
+        const uint32_t bx = base + lane;
+        const bool active = bx < nbx;
+        uint4 wv = make_uint4(0, 0, 0, 0), sv = make_uint4(0, 0, 0, 0);
+        if (active) {
+            wv = *reinterpret_cast<const uint4 *>(words + band_base + 8u * bx);  // sx rows 0..3
+            if (CROSS) sv = *reinterpret_cast<const uint4 *>(snap + band_base + 8u * bx);
+        }
+        const uint32_t wk[4] = {wv.x, wv.y, wv.z, wv.w};
+        const uint32_t sk[4] = {sv.x, sv.y, sv.z, sv.w};
 #pragma unroll
-            for (int f = 0; f < kMomentFields; ++f) red[f][tid] += red[f][tid + off];
-        __syncthreads();
+        for (int r = 0; r < 4; ++r) {
+            // relative sums over the lane's 32 sites of row y = 4 band + r
+            int32_t R = 0, rel1e = 0, rel1o = 0, rel2e = 0, rel2o = 0;
+            int32_t Rs = 0, rel1s = 0, xrel = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t first = (bx == 0u && k == 0) ? 16u : 0u;
+                const uint32_t nib = (wk[r] >> (4 * k)) & 0xFu;
+                const uint32_t e = lut[first + nib];
+                const int32_t s02 = (int32_t)(int8_t)(e & 0xFFu), s13 = (int32_t)(int8_t)((e >> 8) & 0xFFu);
+                const int32_t q02 = (int32_t)((e >> 16) & 31u), q13 = (int32_t)((e >> 21) & 31u);
+                const int32_t T = (int32_t)((e >> 26) & 15u) - 4;
+                // even rows: sites x%4 = 0,2 are the even class (x+y even); odd rows: 1,3
+                const int32_t sE = (r & 1) ? s13 : s02, sO = (r & 1) ? s02 : s13;
+                const int32_t qE = (r & 1) ? q13 : q02, qO = (r & 1) ? q02 : q13;
+                rel1e += 2 * R + sE;
+                rel1o += 2 * R + sO;
+                rel2e += 2 * R * R + 2 * R * sE + qE;
+                rel2o += 2 * R * R + 2 * R * sO + qO;
+                if (CROSS) {
+                    const uint32_t nibs = (sk[r] >> (4 * k)) & 0xFu;
+                    const uint32_t es = lut[first + nibs];
+                    const int32_t ss = (int32_t)(int8_t)(es & 0xFFu) + (int32_t)(int8_t)((es >> 8) & 0xFFu);
+                    const int32_t st = s02 + s13;
+                    xrel += 4 * R * Rs + R * ss + Rs * st + pair[(first << 4) + (nib << 4) + nibs];
+                    rel1s += 4 * Rs + ss;
+                    Rs += (int32_t)((es >> 26) & 15u) - 4;
+                }
+                R += T;
+            }
+            if (!active) {  // lanes past the end of a short band add nothing
+                R = rel1e = rel1o = rel2e = rel2o = 0;
+                Rs = rel1s = xrel = 0;
+            }
+            int32_t tot, tot_s = 0;
+            const int32_t ex = wave_excl_scan_i32(R, tot);
+            const int64_t Ah = (int64_t)h0[4 * band + r] + carry[r] + ex;  // height before the block
+            const int64_t n = active ? 16 : 0;                               // sites per class
+            s1e += n * Ah + rel1e;
+            s1o += n * Ah + rel1o;
+            s2e += n * Ah * Ah + 2 * Ah * rel1e + rel2e;
+            s2o += n * Ah * Ah + 2 * Ah * rel1o + rel2o;
+            carry[r] += tot;
+            if (CROSS) {
+                const int32_t exs = wave_excl_scan_i32(Rs, tot_s);
+                const int64_t As = (int64_t)h0s[4 * band + r] + carry_s[r] + exs;
+                sts += 2 * n * Ah * As + Ah * rel1s + As * (int64_t)(rel1e + rel1o) + xrel;
+                carry_s[r] += tot_s;
+            }
+        }
     }
-    if (tid < kMomentFields) partial[static_cast<uint64_t>(y4) * kMomentFields + tid] = red[tid][0];
+    s1e = wave_sum_i64(s1e);
+    s1o = wave_sum_i64(s1o);
+    s2e = wave_sum_i64(s2e);
+    s2o = wave_sum_i64(s2o);
+    if (CROSS) sts = wave_sum_i64(sts);
+    if (lane == 0) {
+        int64_t *out = partial + static_cast<uint64_t>(band) * kMomentFields;
+        out[0] = s1e;
+        out[1] = s1o;
+        out[2] = s2e;
+        out[3] = s2o;
+        out[4] = sts;
+    }
 }
 
 // 128-bit signed accumulate (two's complement in (lo, hi)).

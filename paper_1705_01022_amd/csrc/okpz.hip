@@ -46,7 +46,7 @@ uint32_t ilog2(uint64_t v)
 }
 
 constexpr uint32_t kMaxL = 1u << 17;
-constexpr uint32_t kMaxLds = 64u * 1024u;
+constexpr uint32_t kMaxLds = 160u * 1024u;  // gfx950 LDS per workgroup
 constexpr uint64_t kMcsLimit = uint64_t(1) << 30;
 
 struct TimedPair {
@@ -73,6 +73,7 @@ struct okpz_lattice {
     bool has_snap = false;
     uint64_t snap_mcs = 0;
     __int128 snap_s1 = 0;
+    uint32_t threads = 0;  // device-step workgroup size (0: default)
     // timing
     bool timing = false;
     std::vector<TimedPair> pairs;
@@ -81,10 +82,36 @@ struct okpz_lattice {
 namespace {
 
 // ---------------------------------------------------------------- validation
+struct WindowShape {
+    uint32_t NWX, NB, P, NR, PY, shared_edges;
+};
+
+// The window of a domain: Dx + 1 sites starting at any column of a block
+// span Dx/32 + 1 blocks (2 for Dx < 32); Dy + 1 rows starting at any row of
+// a band span Dy/4 + 1 bands.
+WindowShape window_shape(const okpz_params &p)
+{
+    WindowShape w;
+    w.NWX = (p.dom_x + 31) / 32 + 1;
+    w.NB = p.dom_y / 4 + 1;
+    w.P = (w.NWX + 1) | 1u;  // odd pitches spread random accesses over the LDS banks
+    w.NR = 4 * w.NB;
+    w.PY = (w.NR + 1) | 1u;
+    w.shared_edges = p.dom_x < 32 ? 1u : 0u;
+    return w;
+}
+
+uint64_t step_lds_bytes(const okpz_params &p)
+{
+    const WindowShape w = window_shape(p);
+    const uint32_t ncell = (p.dom_x / p.cell_x) * (p.dom_y / p.cell_y);
+    return 4ull * step_lds_words(w.NR, w.P, w.NWX, w.PY, w.NB, w.shared_edges, ncell, p.block_scheme == OKPZ_BLOCK_DB);
+}
+
 int check_params(const okpz_params *p)
 {
     if (!p) return OKPZ_EINVAL;
-    if (!is_pow2(p->L) || p->L < 16 || p->L > kMaxL) return OKPZ_EINVAL;
+    if (!is_pow2(p->L) || p->L < 64 || p->L > kMaxL) return OKPZ_EINVAL;
     if (!is_pow2(p->dom_x) || !is_pow2(p->dom_y) || p->dom_x < 4 || p->dom_y < 4) return OKPZ_EINVAL;
     if (2 * p->dom_x > p->L || 2 * p->dom_y > p->L) return OKPZ_EINVAL;
     if (!is_pow2(p->cell_x) || !is_pow2(p->cell_y) || p->cell_x < 2 || p->cell_y < 2) return OKPZ_EINVAL;
@@ -92,10 +119,10 @@ int check_params(const okpz_params *p)
     if (p->block_scheme < OKPZ_BLOCK_DT || p->block_scheme > OKPZ_BLOCK_DTR) return OKPZ_EINVAL;
     if (p->origin_mode < OKPZ_ORIGIN_RANDOM || p->origin_mode > OKPZ_ORIGIN_COARSE) return OKPZ_EINVAL;
     if (p->reserved != 0) return OKPZ_EINVAL;
-    const uint64_t lds = uint64_t(p->dom_x / 4 + 1) * (p->dom_y / 4 + 1) * 4;
-    if (lds > kMaxLds) return OKPZ_EINVAL;
+    if (step_lds_bytes(*p) > kMaxLds) return OKPZ_EINVAL;
     const uint64_t ncell = uint64_t(p->dom_x / p->cell_x) * (p->dom_y / p->cell_y);
     if (ncell > 4096u) return OKPZ_EINVAL;  // at most 16 cells per lane of a 256-thread workgroup
+
     return OKPZ_OK;
 }
 
@@ -208,35 +235,57 @@ void end_timed(okpz_lattice *lat, TimedPair &tp)
     lat->pairs.push_back(tp);
 }
 
+// Workgroup shape of the device step: `threads` lanes (64, 128 or 256; 0
+// picks 256) with ncell / threads cells each (at most 16), fewer lanes when
+// the domain has fewer cells.  Results do not depend on the shape.
+void step_shape(uint32_t ncell, uint32_t threads, uint32_t &cpt, uint32_t &nt)
+{
+    nt = threads ? threads : 256u;
+    if (ncell <= nt) {
+        cpt = 1;
+        nt = std::max<uint32_t>(64, ncell);
+    } else {
+        cpt = ncell / nt;
+    }
+}
+
+template <int SCHEME, bool ACCEPT, int CPT>
+int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
+{
+    if (lds > 64u * 1024u) {
+        static bool raised = false;  // once per kernel instance and process
+        if (!raised) {
+            HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&step_kernel<SCHEME, ACCEPT, CPT>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, CPT>), dim3(ntiles), dim3(nt), lds, st, a);
+    return OKPZ_OK;
+}
+
 template <int SCHEME, bool ACCEPT>
 int launch_step_cpt(uint32_t cpt, uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
     switch (cpt) {
-    case 1: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 1>), dim3(ntiles), dim3(nt), lds, st, a); break;
-    case 2: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 2>), dim3(ntiles), dim3(nt), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 4>), dim3(ntiles), dim3(nt), lds, st, a); break;
-    case 8: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 8>), dim3(ntiles), dim3(nt), lds, st, a); break;
-    case 16: hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, 16>), dim3(ntiles), dim3(nt), lds, st, a); break;
+    case 1: return launch_step_inst<SCHEME, ACCEPT, 1>(nt, ntiles, lds, st, a);
+    case 2: return launch_step_inst<SCHEME, ACCEPT, 2>(nt, ntiles, lds, st, a);
+    case 4: return launch_step_inst<SCHEME, ACCEPT, 4>(nt, ntiles, lds, st, a);
+    case 8: return launch_step_inst<SCHEME, ACCEPT, 8>(nt, ntiles, lds, st, a);
+    case 16: return launch_step_inst<SCHEME, ACCEPT, 16>(nt, ntiles, lds, st, a);
     default: return OKPZ_EINVAL;
     }
-    return OKPZ_OK;
 }
 
 int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
 {
     const okpz_params &p = lat->prm;
     const uint32_t ncell = a.ncell;
-    // workgroups of at most 256 threads (one wave per SIMD); up to 16 cells per lane
-    uint32_t cpt = 1, nt;
-    if (ncell <= 256) {
-        nt = std::max<uint32_t>(64, ncell);
-    } else {
-        cpt = ncell / 256;
-        nt = 256;
-    }
+    uint32_t cpt, nt;
+    step_shape(ncell, lat->threads, cpt, nt);
     if (cpt > 16) return OKPZ_EINVAL;
     const uint32_t ntiles = (p.L / (2 * p.dom_x)) * (p.L / (2 * p.dom_y));
-    const size_t lds = size_t(a.pitch) * a.Wy * sizeof(uint32_t);
+    const size_t lds = step_lds_bytes(p);
     int rc;
     switch (p.block_scheme * 2 + (accept ? 1 : 0)) {
     case 0: rc = launch_step_cpt<kDT, false>(cpt, nt, ntiles, lds, lat->stream, a); break;
@@ -254,11 +303,13 @@ int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
 StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double pd, double qr)
 {
     const okpz_params &p = lat->prm;
+    const WindowShape ws = window_shape(p);
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.words = lat->words;
-    a.lw_log2 = ilog2(p.L / 4);
-    a.lw_mask = p.L / 4 - 1;
+    a.nbx_log2 = ilog2(p.L / 32);
+    a.nbx_mask = p.L / 32 - 1;
+    a.nby_mask = p.L / 4 - 1;
     a.L_mask = p.L - 1;
     a.Dx = p.dom_x;
     a.Dy = p.dom_y;
@@ -272,11 +323,13 @@ StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double pd, doub
     a.s_bits = ls.s_bits;
     a.F_log2 = ls.F_log2;
     a.rounds = p.cell_x * p.cell_y;
-    a.Wx = p.dom_x / 4 + 1;
-    a.Wy = p.dom_y / 4 + 1;
-    a.pitch = a.Wx;
-    a.dep_always = pd == 1.0;
-    a.rem_always = qr == 1.0;
+    a.NWX = ws.NWX;
+    a.NB = ws.NB;
+    a.P = ws.P;
+    a.NR = ws.NR;
+    a.PY = ws.PY;
+    a.shared_edges = ws.shared_edges;
+    a.flip_table = (pd == 1.0 ? 1u << kPatternMin : 0u) | (qr == 1.0 ? 1u << kPatternMax : 0u);
     a.P_hi = (uint32_t)(ls.P >> 32);
     a.P_lo = (uint32_t)ls.P;
     a.Q_hi = (uint32_t)(ls.Q >> 32);
@@ -287,8 +340,7 @@ StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double pd, doub
 int fill_flat(okpz_lattice *lat)
 {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(4096, (lat->nwords + 255) / 256);
-    hipLaunchKernelGGL(fill_words_kernel, dim3(blocks), dim3(256), 0, lat->stream, lat->words, lat->nwords,
-                       kFlatWord);
+    hipLaunchKernelGGL(fill_flat_kernel, dim3(blocks), dim3(256), 0, lat->stream, lat->words, lat->nwords);
     HIP_TRY(hipGetLastError());
     lat->mcs = 0;
     lat->has_snap = false;
@@ -301,16 +353,18 @@ int fill_flat(okpz_lattice *lat)
 int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_dst)
 {
     const okpz_params &p = lat->prm;
-    const uint32_t lw_log2 = ilog2(p.L / 4);
+    const uint32_t nbx_log2 = ilog2(p.L / 32);
     TimedPair tp;
     begin_timed(lat, 1, tp);
-    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, lat->stream, src, p.L, lw_log2, h0_dst);
+    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, lat->stream, src, p.L, nbx_log2, h0_dst);
+    const uint32_t rows_per_block = kMeasureThreads / 64;
+    const uint32_t blocks = (p.L / 4 + rows_per_block - 1) / rows_per_block;
     if (cross)
-        hipLaunchKernelGGL((rows_kernel<true>), dim3(p.L / 4), dim3(kMeasureThreads), 0, lat->stream, src,
-                           h0_dst, lat->snap, lat->h0s, p.L, lw_log2, lat->partial);
+        hipLaunchKernelGGL((rows_kernel<true>), dim3(blocks), dim3(kMeasureThreads), 0, lat->stream, src, h0_dst,
+                           lat->snap, lat->h0s, p.L, nbx_log2, lat->partial);
     else
-        hipLaunchKernelGGL((rows_kernel<false>), dim3(p.L / 4), dim3(kMeasureThreads), 0, lat->stream, src,
-                           h0_dst, nullptr, nullptr, p.L, lw_log2, lat->partial);
+        hipLaunchKernelGGL((rows_kernel<false>), dim3(blocks), dim3(kMeasureThreads), 0, lat->stream, src, h0_dst,
+                           nullptr, nullptr, p.L, nbx_log2, lat->partial);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, lat->stream, lat->partial, p.L / 4, lat->reduced);
     end_timed(lat, tp);
     HIP_TRY(hipGetLastError());
@@ -341,25 +395,25 @@ void fill_moments(const okpz_lattice *lat, okpz_moments *out)
     out->w2_sub = std::ldexp(i128_to_double(2 * ((ne * s2e - s1e * s1e) + (no * s2o - s1o * s1o))), -sh);
 }
 
-// host packing / unpacking
+void fill_correlation(const okpz_lattice *lat, okpz_correlation *out);
+
+// host packing / unpacking: site (x, y) lives in block (x/32, y/4), word
+// 8 * block + y%4 (sx) or 8 * block + 4 + y%4 (sy), bit x%32
+inline uint64_t sx_word(uint32_t L, uint32_t x, uint32_t y)
+{
+    return (((uint64_t)(y >> 2) * (L / 32) + (x >> 5)) << 3) + (y & 3);
+}
+
 void pack_sites(const uint8_t *sites, uint32_t L, uint32_t *words)
 {
-    const uint32_t lw = L / 4;
-    std::memset(words, 0, sizeof(uint32_t) * (size_t)lw * lw);
+    std::memset(words, 0, sizeof(uint32_t) * (size_t)L * L / 16);
     for (uint32_t y = 0; y < L; ++y)
         for (uint32_t x = 0; x < L; ++x) {
             const uint8_t v = sites[(size_t)y * L + x];
-            const uint32_t bit = 4 * (y & 3) + (x & 3);
-            uint32_t &w = words[(size_t)(y >> 2) * lw + (x >> 2)];
-            w |= (uint32_t)(v & 1) << bit;
-            w |= (uint32_t)((v >> 1) & 1) << (16 + bit);
+            const uint64_t w = sx_word(L, x, y);
+            words[w] |= (uint32_t)(v & 1) << (x & 31);
+            words[w + 4] |= (uint32_t)((v >> 1) & 1) << (x & 31);
         }
-}
-
-inline uint8_t site_of(uint32_t w, uint32_t x, uint32_t y)
-{
-    const uint32_t bit = 4 * (y & 3) + (x & 3);
-    return (uint8_t)(((w >> bit) & 1) | (((w >> (16 + bit)) & 1) << 1));
 }
 
 bool valid_surface(const uint8_t *s, uint32_t L)
@@ -389,20 +443,35 @@ bool valid_surface(const uint8_t *s, uint32_t L)
     return true;
 }
 
-// copy word rows [wy0, wy0+nwy) x word columns [wx0, wx0+nwx) (periodic) to host
-int read_word_block(okpz_lattice *lat, uint32_t wx0, uint32_t wy0, uint32_t nwx, uint32_t nwy,
-                    std::vector<uint32_t> &buf)
+// The blocks covering a site window: bands by0 .. by0+nby-1 and blocks
+// bx0 .. bx0+nbx-1 of each band (periodic), 8 words each, as
+// buf[(band * nbx + block) * 8 + word].
+struct BlockRect {
+    uint32_t bx0, by0, nbx, nby;
+};
+
+BlockRect rect_of(uint32_t L, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h)
 {
-    const uint32_t lw = lat->prm.L / 4;
-    buf.assign((size_t)nwx * nwy, 0);
-    for (uint32_t r = 0; r < nwy; ++r) {
-        const uint32_t gy = (wy0 + r) % lw;
+    BlockRect r;
+    r.bx0 = x0 >> 5;
+    r.by0 = y0 >> 2;
+    r.nbx = std::min(L / 32, ((x0 & 31) + w + 31) / 32);
+    r.nby = std::min(L / 4, ((y0 & 3) + h + 3) / 4);
+    return r;
+}
+
+int read_blocks(okpz_lattice *lat, const BlockRect &r, std::vector<uint32_t> &buf)
+{
+    const uint32_t nbx_all = lat->prm.L / 32, nby_all = lat->prm.L / 4;
+    buf.assign((size_t)r.nbx * r.nby * 8, 0);
+    for (uint32_t b = 0; b < r.nby; ++b) {
+        const uint64_t band = (uint64_t)((r.by0 + b) % nby_all) * nbx_all;
         uint32_t done = 0;
-        while (done < nwx) {
-            const uint32_t gx = (wx0 + done) % lw;
-            const uint32_t run = std::min(nwx - done, lw - gx);
-            HIP_TRY(hipMemcpyAsync(&buf[(size_t)r * nwx + done], lat->words + (size_t)gy * lw + gx,
-                                   run * sizeof(uint32_t), hipMemcpyDeviceToHost, lat->stream));
+        while (done < r.nbx) {
+            const uint32_t gx = (r.bx0 + done) % nbx_all;
+            const uint32_t run = std::min(r.nbx - done, nbx_all - gx);
+            HIP_TRY(hipMemcpyAsync(&buf[((size_t)b * r.nbx + done) * 8], lat->words + (band + gx) * 8,
+                                   run * 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, lat->stream));
             done += run;
         }
     }
@@ -410,23 +479,30 @@ int read_word_block(okpz_lattice *lat, uint32_t wx0, uint32_t wy0, uint32_t nwx,
     return OKPZ_OK;
 }
 
-int write_word_block(okpz_lattice *lat, uint32_t wx0, uint32_t wy0, uint32_t nwx, uint32_t nwy,
-                     const std::vector<uint32_t> &buf)
+int write_blocks(okpz_lattice *lat, const BlockRect &r, const std::vector<uint32_t> &buf)
 {
-    const uint32_t lw = lat->prm.L / 4;
-    for (uint32_t r = 0; r < nwy; ++r) {
-        const uint32_t gy = (wy0 + r) % lw;
+    const uint32_t nbx_all = lat->prm.L / 32, nby_all = lat->prm.L / 4;
+    for (uint32_t b = 0; b < r.nby; ++b) {
+        const uint64_t band = (uint64_t)((r.by0 + b) % nby_all) * nbx_all;
         uint32_t done = 0;
-        while (done < nwx) {
-            const uint32_t gx = (wx0 + done) % lw;
-            const uint32_t run = std::min(nwx - done, lw - gx);
-            HIP_TRY(hipMemcpyAsync(lat->words + (size_t)gy * lw + gx, &buf[(size_t)r * nwx + done],
-                                   run * sizeof(uint32_t), hipMemcpyHostToDevice, lat->stream));
+        while (done < r.nbx) {
+            const uint32_t gx = (r.bx0 + done) % nbx_all;
+            const uint32_t run = std::min(r.nbx - done, nbx_all - gx);
+            HIP_TRY(hipMemcpyAsync(lat->words + (band + gx) * 8, &buf[((size_t)b * r.nbx + done) * 8],
+                                   run * 8 * sizeof(uint32_t), hipMemcpyHostToDevice, lat->stream));
             done += run;
         }
     }
     HIP_TRY(hipStreamSynchronize(lat->stream));
     return OKPZ_OK;
+}
+
+// word of buf holding row gy of (global) column gx, relative to the rectangle
+inline size_t rect_word(uint32_t L, const BlockRect &r, uint32_t gx, uint32_t gy)
+{
+    const uint32_t bx = ((gx >> 5) + L / 32 - r.bx0) % (L / 32);
+    const uint32_t by = ((gy >> 2) + L / 4 - r.by0) % (L / 4);
+    return ((size_t)by * r.nbx + bx) * 8 + (gy & 3);
 }
 
 void release(okpz_lattice *lat)
@@ -617,12 +693,33 @@ int okpz_snapshot(okpz_lattice *lat)
     return OKPZ_OK;
 }
 
+int okpz_observe(okpz_lattice *lat, okpz_moments *moments, okpz_correlation *corr)
+{
+    if (!lat || !moments) return OKPZ_EINVAL;
+    if (corr && !lat->has_snap) return OKPZ_ESTATE;
+    const int rc = run_measure(lat, corr != nullptr, lat->words, lat->h0);
+    if (rc != OKPZ_OK) return rc;
+    fill_moments(lat, moments);
+    if (corr) fill_correlation(lat, corr);
+    return OKPZ_OK;
+}
+
 int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out)
 {
     if (!lat || !out) return OKPZ_EINVAL;
     if (!lat->has_snap) return OKPZ_ESTATE;
     const int rc = run_measure(lat, true, lat->words, lat->h0);
     if (rc != OKPZ_OK) return rc;
+    fill_correlation(lat, out);
+    return OKPZ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void fill_correlation(const okpz_lattice *lat, okpz_correlation *out)
+{
     const uint64_t L = lat->prm.L;
     const __int128 n = (__int128)L * L;
     const __int128 s1t = pair_to_i128(lat->host_out + 0) + pair_to_i128(lat->host_out + 2);
@@ -633,8 +730,11 @@ int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out)
     out->s1_t = to_abi(s1t);
     out->s1_s = to_abi(lat->snap_s1);
     out->c_h = std::ldexp(i128_to_double(n * sts - s1t * lat->snap_s1), -4 * (int)ilog2(L));
-    return OKPZ_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int okpz_get_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uint32_t h, uint8_t *sites)
 {
@@ -643,17 +743,15 @@ int okpz_get_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uin
     if (w == 0 || h == 0 || w > L || h > L) return OKPZ_EINVAL;
     x0 &= L - 1;
     y0 &= L - 1;
-    const uint32_t wx0 = x0 >> 2, wy0 = y0 >> 2;
-    const uint32_t nwx = std::min(L / 4, ((x0 & 3) + w + 3) / 4);
-    const uint32_t nwy = std::min(L / 4, ((y0 & 3) + h + 3) / 4);
+    const BlockRect r = rect_of(L, x0, y0, w, h);
     std::vector<uint32_t> buf;
-    const int rc = read_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    const int rc = read_blocks(lat, r, buf);
     if (rc != OKPZ_OK) return rc;
     for (uint32_t j = 0; j < h; ++j)
         for (uint32_t i = 0; i < w; ++i) {
             const uint32_t gx = (x0 + i) & (L - 1), gy = (y0 + j) & (L - 1);
-            const uint32_t bx = ((gx >> 2) - wx0) & (L / 4 - 1), by = ((gy >> 2) - wy0) & (L / 4 - 1);
-            sites[(size_t)j * w + i] = site_of(buf[(size_t)by * nwx + bx], gx, gy);
+            const size_t wi = rect_word(L, r, gx, gy);
+            sites[(size_t)j * w + i] = (uint8_t)(((buf[wi] >> (gx & 31)) & 1) | (((buf[wi + 4] >> (gx & 31)) & 1) << 1));
         }
     return OKPZ_OK;
 }
@@ -667,23 +765,20 @@ int okpz_set_window(okpz_lattice *lat, uint32_t x0, uint32_t y0, uint32_t w, uin
         if (sites[i] & ~3u) return OKPZ_EINVAL;
     x0 &= L - 1;
     y0 &= L - 1;
-    const uint32_t wx0 = x0 >> 2, wy0 = y0 >> 2;
-    const uint32_t nwx = std::min(L / 4, ((x0 & 3) + w + 3) / 4);
-    const uint32_t nwy = std::min(L / 4, ((y0 & 3) + h + 3) / 4);
+    const BlockRect r = rect_of(L, x0, y0, w, h);
     std::vector<uint32_t> buf;
-    int rc = read_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    const int rc = read_blocks(lat, r, buf);
     if (rc != OKPZ_OK) return rc;
     for (uint32_t j = 0; j < h; ++j)
         for (uint32_t i = 0; i < w; ++i) {
             const uint32_t gx = (x0 + i) & (L - 1), gy = (y0 + j) & (L - 1);
-            const uint32_t bx = ((gx >> 2) - wx0) & (L / 4 - 1), by = ((gy >> 2) - wy0) & (L / 4 - 1);
-            uint32_t &word = buf[(size_t)by * nwx + bx];
-            const uint32_t bit = 4 * (gy & 3) + (gx & 3);
+            const size_t wi = rect_word(L, r, gx, gy);
+            const uint32_t bit = 1u << (gx & 31);
             const uint8_t v = sites[(size_t)j * w + i];
-            word &= ~((1u << bit) | (1u << (16 + bit)));
-            word |= ((uint32_t)(v & 1) << bit) | ((uint32_t)((v >> 1) & 1) << (16 + bit));
+            buf[wi] = (buf[wi] & ~bit) | ((v & 1) ? bit : 0u);
+            buf[wi + 4] = (buf[wi + 4] & ~bit) | ((v & 2) ? bit : 0u);
         }
-    return write_word_block(lat, wx0, wy0, nwx, nwy, buf);
+    return write_blocks(lat, r, buf);
 }
 
 int okpz_get_sites(okpz_lattice *lat, uint8_t *sites)
@@ -730,6 +825,18 @@ int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs)
 {
     if (!lat || !mcs) return OKPZ_EINVAL;
     *mcs = lat->mcs;
+    return OKPZ_OK;
+}
+
+int okpz_set_threads(okpz_lattice *lat, uint32_t threads)
+{
+    if (!lat) return OKPZ_EINVAL;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256) return OKPZ_EINVAL;
+    const uint32_t ncell = (lat->prm.dom_x / lat->prm.cell_x) * (lat->prm.dom_y / lat->prm.cell_y);
+    uint32_t cpt, nt;
+    step_shape(ncell, threads, cpt, nt);
+    if (cpt > 16) return OKPZ_EINVAL;
+    lat->threads = threads;
     return OKPZ_OK;
 }
 

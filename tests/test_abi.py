@@ -76,6 +76,7 @@ def test_struct_layouts_match_c(okpz, tmp_path):
     ((1 << 17, 256, 256, 8, 8, 1), True),
     ((4096, 256, 128, 4, 16, 2), True),
     ((64, 16, 16, 8, 8, 3), False),       # bad scheme
+    ((32, 8, 8, 4, 4, 0), False),         # L below two 32-site blocks
     ((96, 16, 16, 8, 8, 0), False),       # L not a power of two
     ((64, 64, 16, 8, 8, 0), False),       # tile wider than the lattice
     ((64, 2, 16, 2, 2, 0), False),        # domain narrower than a word

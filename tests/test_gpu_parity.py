@@ -45,7 +45,7 @@ def test_philox_device_matches_oracle(okpz, orc):
 
 
 def test_flat_state_and_moments(okpz, orc):
-    for L in (16, 64, 256, 4096):
+    for L in (64, 128, 256, 4096):
         with lattice(okpz, L=L, Dx=min(16, L // 2), Dy=min(16, L // 2)) as lat:
             s = lat.sites()
             assert np.array_equal(s, orc.init_flat(L))
@@ -82,9 +82,14 @@ def test_rates(okpz, orc, scheme, pq):
 
 
 SHAPES = [
-    # L, Dx, Dy, Cx, Cy : several tiles, cells per domain from 1 to 16384,
-    # fewer cells than a wave (ragged workgroups), rectangular domains/cells
+    # L, Dx, Dy, Cx, Cy : several tiles, cells per domain from 1 to 4096,
+    # fewer cells than a wave (ragged workgroups), rectangular domains/cells,
+    # domains narrower than a 32-site block (edge blocks shared by two
+    # domains of one set) and exactly one block wide
     (64, 16, 16, 2, 2),
+    (64, 32, 32, 8, 8),
+    (128, 32, 8, 4, 2),
+    (128, 8, 32, 2, 8),
     (64, 8, 8, 8, 8),
     (64, 4, 4, 2, 2),
     (128, 32, 16, 4, 2),
@@ -169,6 +174,50 @@ def test_autocorr_and_snapshot(okpz, orc):
             assert ac["t"] == m + 1 and ac["s"] == 5
             assert ac["s_ts"] == orc.cross(ref, snap)
             assert ac["c_h"] == orc.c_h(ref, snap)
+
+
+def test_observe_matches_measure_and_autocorr(okpz, orc):
+    e = emulator(orc, L=128, Dx=32, Dy=32, scheme=2, p=0.7, q=0.4)
+    ref = orc.init_flat(128)
+    with lattice(okpz, L=128, Dx=32, Dy=32, scheme=2) as lat:
+        mo, ac = lat.observe(False)
+        assert ac is None and mo["w2"] == 0.25
+        with pytest.raises(okpz.OkpzError):
+            lat.observe(True)
+        lat.run(3, 0.7, 0.4)
+        for m in range(3):
+            e.mcs(ref, m)
+        lat.snapshot()
+        snap = ref.copy()
+        for m in range(3, 9):
+            lat.run(1, 0.7, 0.4)
+            e.mcs(ref, m)
+            mo, ac = lat.observe(True)
+            check_moments(orc, mo, ref)
+            assert mo == lat.measure()
+            assert ac == lat.autocorr()
+            assert ac["c_h"] == orc.c_h(ref, snap)
+
+
+@pytest.mark.parametrize("scheme,pq,shape", [(0, (1.0, 0.0), (256, 64, 64, 4, 4)),
+                                             (1, (0.95, 0.05), (512, 128, 128, 8, 8)),
+                                             (2, (0.7, 0.2), (512, 256, 128, 8, 4))])
+def test_workgroup_shape_does_not_change_results(okpz, orc, scheme, pq, shape):
+    L, Dx, Dy, Cx, Cy = shape
+    e = emulator(orc, L=L, Dx=Dx, Dy=Dy, Cx=Cx, Cy=Cy, scheme=scheme, p=pq[0], q=pq[1])
+    ref = orc.init_flat(L)
+    for m in range(3):
+        e.mcs(ref, m)
+    ncell = (Dx // Cx) * (Dy // Cy)
+    for threads in (0, 64, 128, 256):
+        with lattice(okpz, L=L, Dx=Dx, Dy=Dy, Cx=Cx, Cy=Cy, scheme=scheme) as lat:
+            if ncell // threads > 16 if threads else False:
+                with pytest.raises(okpz.OkpzError):
+                    lat.set_threads(threads)
+                continue
+            lat.set_threads(threads)
+            lat.run(3, *pq)
+            assert np.array_equal(lat.sites(), ref), threads
 
 
 def test_determinism_and_resume(okpz):
