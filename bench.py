@@ -28,8 +28,25 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # VALU issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (32-bit integer lane ops)
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# algorithmic integer lane-ops per update attempt of the method (derivation in the design doc)
-OPS_PER_ATTEMPT = {"DB_accept": 40.0, "DT_noaccept": 28.0}
+
+
+def ops_per_attempt(scheme: int, cell: int, accept: bool) -> float:
+    """Algorithmic 32-bit VALU issue slots one update attempt needs (the design doc,
+    "ALU roofline"): its share of a Philox4x32-10 block (100 slots: 10 rounds
+    of two quarter-rate 32x32->64 multiplies and two 3-input XORs) for an
+    F-bit field, plus field extraction (1), site selection (4 for a fixed
+    cell grid, 8 with the per-round cell shift), word/bit addressing (5),
+    reading the four slopes (6), the decision (1, or 5 with an acceptance
+    draw) and the flip masks (3)."""
+    sites = cell * cell if scheme == 1 else cell * cell // 4
+    s_bits = max(0, sites.bit_length() - 1)
+    if accept:
+        F = 1 << (s_bits + 8 - 1).bit_length()
+    else:
+        F = 1 << (max(s_bits, 1) - 1).bit_length()
+    rng = 100.0 * F / 128.0
+    select = 4 if scheme == 0 else 8
+    return rng + 1 + select + 5 + 6 + (5 if accept else 1) + 3
 
 WORKLOADS = {
     # name: (L, D, C, scheme, p, q, label)
@@ -121,7 +138,7 @@ def main():
     bytes_per_launch = sites / 8
     attempts_per_launch = sites / 4
     accept = not (p in (0.0, 1.0) and q in (0.0, 1.0))
-    ops = OPS_PER_ATTEMPT["DB_accept" if accept else "DT_noaccept"]
+    ops = ops_per_attempt(scheme, C, accept)
     alu_achieved = attempts_per_launch * ops / step_avg_s / 1e9
     hbm_achieved = bytes_per_launch / step_avg_s / 1e9
     line = {
