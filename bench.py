@@ -86,6 +86,46 @@ def cpu_baseline(L, D, C, scheme, p, q, budget_s=15.0):
                       % (m - 1, W, W, W // (2 * D), W // (2 * D), L, attempts, el)}
 
 
+def batched_comparison(okpz, n_batched=200, n_plain=4, tune_mcs=10):
+    """The batched workload (512 realisations, L in {256..2048}, (1,0) or
+    (1/2,1/2), DTrDT, D = min(256, L/2), TC=1,1): one persistent launch per
+    run (graph-captured, launch shape autotuned) against the plain path that
+    runs one lattice per launch (okpz_run, 4 device-step launches per MCS)."""
+    from workloads import batched_composition
+
+    comp = batched_composition(512, 1)
+    b = okpz.Batch()
+    lats = [b.lattice(c.L, c.Dx, c.Dy, c.Cx, c.Cy, c.scheme, seed=1, stream=c.stream) for c in comp]
+    P, Q = [c.p for c in comp], [c.q for c in comp]
+    sites = sum(c.L * c.L for c in comp)
+    n = len(comp)
+    tuned = b.tune([tune_mcs] * n, P, Q)
+    b.sync()
+    b.timing(True)
+    t0 = time.perf_counter()
+    b.run([n_batched] * n, P, Q)
+    b.sync()
+    el_b = time.perf_counter() - t0
+    gpu_ms = b.get_timing()["ms"]
+    b.timing(False)
+    t0 = time.perf_counter()
+    for lat, c in zip(lats, comp):
+        lat.run(n_plain, c.p, c.q)
+    b.sync()
+    el_p = time.perf_counter() - t0
+    b.close()
+    batched = sites * n_batched / el_b
+    plain = sites * n_plain / el_p
+    best = tuned["best"]
+    return {"workload": "512 realisations, L uniform in {256,512,1024,2048}, (p,q)=(1,0)|(1/2,1/2), "
+                        "DTrDT, D=min(256,L/2), TC=1,1",
+            "sites": sites, "batched_attempts_per_s": batched, "batched_mcs": n_batched,
+            "batched_kernel_ms": gpu_ms, "plain_attempts_per_s": plain, "plain_mcs": n_plain,
+            "batched_over_plain": batched / plain,
+            "launch_shape": {"threads": best[0], "grid_fraction": best[1], "graph": best[2]},
+            "tuner_ms": {"%d/%.2f/%s" % k: v for k, v in tuned["times_ms"].items()}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +134,7 @@ def main():
     ap.add_argument("--workload", default="L131072", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -181,6 +222,9 @@ def main():
                           "hardware": "Kepler GTX Titan Black / Tesla K80, DTrDB, L=2^16"},
     }
     lat.close()
+    if not args.no_batched:
+        print("bench: batched vs plain", file=sys.stderr, flush=True)
+        line["batched"] = batched_comparison(okpz)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (about %.0f s)" % args.cpu_budget, file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(L, D, C, scheme, p, q, args.cpu_budget)

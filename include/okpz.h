@@ -57,6 +57,7 @@ extern "C" {
 #define OKPZ_EHIP (-3)      /* HIP runtime error, see okpz_last_error()        */
 #define OKPZ_EOVERFLOW (-4) /* a counter or an exact reduction would overflow  */
 #define OKPZ_ESTATE (-5)    /* call not valid in the current state             */
+#define OKPZ_EWAIT (-6)     /* a batch kernel's dependency wait timed out      */
 
 /* block-level (thread-cell) decomposition schemes, Sec. 3.1 */
 #define OKPZ_BLOCK_DT 0  /* single-hit double tiling: random quadrant per round  */
@@ -270,6 +271,78 @@ int okpz_get_timing(okpz_lattice *lat, double *step_ms, uint64_t *step_launches,
  * For testing the generator the step kernel uses.  Synchronous.
  */
 int okpz_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, size_t n);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent lattices (realisations, each with its own
+ * size, decomposition, seed/stream and rates) advanced together by ONE
+ * persistent kernel launch per okpz_batch_run call.  The launch hands out
+ * work items (lattice, MCS, device step, tile) in MCS-major order from a
+ * device-wide queue; an item starts once its lattice's previous device step
+ * has finished on every tile, i.e. each lattice keeps the step order of
+ * Sec. 3 / Sec. 3.1 (DTr at device level) while the steps of different
+ * lattices overlap.  Every member's result is bit-identical to running it
+ * alone with okpz_run (random draws are keyed by lattice, MCS, step, tile,
+ * cell and round only).
+ *
+ * Members are ordinary okpz_lattice handles created on the batch's stream;
+ * the batch does not own them.  All members share one block scheme.  Every
+ * okpz_* call on a member (measure, snapshot, get_sites, run, ...) stays
+ * valid and is ordered with the batch's work on the shared stream.  Remove
+ * a member before destroying it.
+ *
+ * Launches are captured once into a HIP graph and replayed while the
+ * membership, the per-member MCS counts and rates, and the launch shape stay
+ * the same (not available on the null stream).
+ * ------------------------------------------------------------------------ */
+typedef struct okpz_batch okpz_batch;
+
+/* New empty batch whose work runs on hip_stream (a hipStream_t, or NULL:
+ * the null stream, then without graph capture). */
+int okpz_batch_create(void *hip_stream, okpz_batch **out);
+
+/* Synchronise and free the batch (not its members). */
+int okpz_batch_destroy(okpz_batch *batch);
+
+/* Add a lattice; *slot receives its index (the lowest free one).  EINVAL if
+ * the lattice is already a member, uses another stream or another block
+ * scheme than the current members. */
+int okpz_batch_add(okpz_batch *batch, okpz_lattice *lat, int32_t *slot);
+
+/* Remove the member at slot (synchronises the stream first). */
+int okpz_batch_remove(okpz_batch *batch, int32_t slot);
+
+/* Number of slot indices in use (highest member index + 1); the arrays of
+ * okpz_batch_run have this length. */
+int okpz_batch_size(const okpz_batch *batch, uint32_t *nslots);
+
+/*
+ * Launch shape (physical mapping only; results do not depend on it):
+ * threads per workgroup (64, 128, 256, or 0 = 256), persistent workgroups
+ * (0 = as many as fit on the device at once), use_graph (capture and replay
+ * the launch).  Chosen by the autotuner of the Python layer.
+ */
+int okpz_batch_config(okpz_batch *batch, uint32_t threads, uint32_t grid, int use_graph);
+
+/*
+ * Advance member s by n_mcs[s] MCS at rates p[s], q[s] (Sec. 2.1 rule),
+ * for every slot s < okpz_batch_size (n_mcs[s] = 0: member idle; free
+ * slots must have n_mcs = 0).  Asynchronous on the batch's stream; the host
+ * arrays may be reused on return.  Everything is validated before anything
+ * runs (EINVAL, EOVERFLOW past 2^30 MCS).  Runs longer than 2^31 / (4 x
+ * tiles) MCS of any member are split into several launches.
+ * EWAIT if an earlier launch of this batch failed (see okpz_batch_sync).
+ */
+int okpz_batch_run(okpz_batch *batch, const uint64_t *n_mcs, const double *p, const double *q);
+
+/* Wait for the batch's work; OKPZ_EWAIT if a launch stopped on a timed-out
+ * dependency wait (the members' lattices are then undefined and the batch
+ * refuses further runs). */
+int okpz_batch_sync(okpz_batch *batch);
+
+/* HIP-event timing of the batch launches (as okpz_timing); get_timing
+ * returns total milliseconds, launches and update attempts since enabled. */
+int okpz_batch_timing(okpz_batch *batch, int enable);
+int okpz_batch_get_timing(okpz_batch *batch, double *ms, uint64_t *launches, uint64_t *attempts);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libokpz.so")
 
-OK, EINVAL, ENOMEM, EHIP, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, EOVERFLOW, ESTATE, EWAIT = 0, -1, -2, -3, -4, -5, -6
 BLOCK_DT, BLOCK_DB, BLOCK_DTR = 0, 1, 2
 ORIGIN_RANDOM, ORIGIN_FIXED, ORIGIN_COARSE = 0, 1, 2
 SCHEMES = {"DT": BLOCK_DT, "DB": BLOCK_DB, "DTR": BLOCK_DTR, "DTr": BLOCK_DTR}
@@ -119,6 +119,18 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64)]),
     "okpz_philox": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _P, _P, ctypes.c_size_t]),
+    "okpz_batch_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "okpz_batch_destroy": (ctypes.c_int, [_P]),
+    "okpz_batch_add": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "okpz_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "okpz_batch_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "okpz_batch_config": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
+    "okpz_batch_run": (ctypes.c_int, [_P, _P, _P, _P]),
+    "okpz_batch_sync": (ctypes.c_int, [_P]),
+    "okpz_batch_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "okpz_batch_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_uint64),
+                                              ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -322,6 +334,136 @@ class Lattice:
                                       ctypes.byref(mn)), "okpz_get_timing")
         return {"step_ms": sm.value, "step_launches": sn.value,
                 "measure_ms": mm.value, "measure_launches": mn.value}
+
+
+class Batch:
+    """Many lattices advanced together by one persistent kernel launch per run.
+
+    Members are ordinary :class:`Lattice` objects on the batch's HIP stream
+    (``Batch.lattice`` creates one); each keeps its full single-lattice API.
+    ``hip_stream``: a raw hipStream_t; by default the batch creates its own
+    torch stream (graph capture needs a non-null stream).
+    """
+
+    def __init__(self, hip_stream=None):
+        lib = load()
+        self._torch_stream = None
+        if hip_stream is None:
+            import torch
+
+            self._torch_stream = torch.cuda.Stream()
+            hip_stream = self._torch_stream.cuda_stream
+        self.hip_stream = hip_stream
+        h = ctypes.c_void_p()
+        _check(lib.okpz_batch_create(ctypes.c_void_p(hip_stream) if hip_stream else None, ctypes.byref(h)),
+               "okpz_batch_create")
+        self._h = h
+        self.members = {}
+
+    def lattice(self, L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0, origin_mode=ORIGIN_RANDOM,
+                add=True) -> Lattice:
+        """A new lattice on the batch's stream (added as a member unless add=False)."""
+        lat = Lattice(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode, hip_stream=self.hip_stream)
+        if add:
+            self.add(lat)
+        return lat
+
+    def add(self, lat: Lattice) -> int:
+        slot = ctypes.c_int32()
+        _check(load().okpz_batch_add(self._h, lat._h, ctypes.byref(slot)), "okpz_batch_add")
+        self.members[slot.value] = lat
+        lat.slot = slot.value
+        return slot.value
+
+    def remove(self, slot: int):
+        _check(load().okpz_batch_remove(self._h, slot), "okpz_batch_remove")
+        self.members.pop(slot, None)
+
+    @property
+    def size(self) -> int:
+        n = ctypes.c_uint32()
+        _check(load().okpz_batch_size(self._h, ctypes.byref(n)), "okpz_batch_size")
+        return n.value
+
+    def config(self, threads: int = 0, grid: int = 0, use_graph: bool = True):
+        """Launch shape only (results do not depend on it)."""
+        _check(load().okpz_batch_config(self._h, threads, grid, int(use_graph)), "okpz_batch_config")
+        self._config = (threads, grid, use_graph)
+
+    def run(self, n_mcs, p, q):
+        """n_mcs, p, q: dicts slot -> value or sequences indexed by slot (0 MCS = idle)."""
+        n = self.size
+        nm = np.zeros(n, dtype=np.uint64)
+        pp = np.zeros(n, dtype=np.float64)
+        qq = np.zeros(n, dtype=np.float64)
+        for arr, src in ((nm, n_mcs), (pp, p), (qq, q)):
+            if isinstance(src, dict):
+                for k, v in src.items():
+                    arr[k] = v
+            elif np.isscalar(src):
+                arr[[k for k in self.members]] = src
+            else:
+                arr[:len(src)] = src
+        _check(load().okpz_batch_run(self._h, _ptr(nm), _ptr(pp), _ptr(qq)), "okpz_batch_run")
+
+    def sync(self):
+        _check(load().okpz_batch_sync(self._h), "okpz_batch_sync")
+
+    def timing(self, enable: bool = True):
+        _check(load().okpz_batch_timing(self._h, int(enable)), "okpz_batch_timing")
+
+    def get_timing(self) -> dict:
+        ms, nl, na = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().okpz_batch_get_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(na)),
+               "okpz_batch_get_timing")
+        return {"ms": ms.value, "launches": nl.value, "attempts": na.value}
+
+    def tune(self, n_mcs, p, q, candidates=None) -> dict:
+        """Autotune the launch shape on real work: run ``n_mcs`` (per member)
+        under each candidate (threads, grid fraction, graph) and keep the
+        fastest.  Every candidate's MCS really advance the members (results do
+        not depend on the shape).  Returns {candidate: ms} and the choice."""
+        if candidates is None:
+            candidates = [(256, 1.0, True), (128, 1.0, True), (256, 0.5, True), (256, 1.0, False)]
+        full = self._full_grid()
+        times = {}
+        for threads, frac, graph in candidates:
+            grid = max(1, int(full * frac)) if frac < 1.0 else 0
+            self.config(threads, grid, graph)
+            self.run(n_mcs, p, q)  # warm (captures the graph)
+            self.sync()
+            self.timing(True)
+            self.run(n_mcs, p, q)
+            self.sync()
+            times[(threads, frac, graph)] = self.get_timing()["ms"]
+            self.timing(False)
+        best = min(times, key=times.get)
+        threads, frac, graph = best
+        self.config(threads, max(1, int(full * frac)) if frac < 1.0 else 0, graph)
+        return {"times_ms": times, "best": best}
+
+    @staticmethod
+    def _full_grid() -> int:
+        import torch
+
+        return torch.cuda.get_device_properties(0).multi_processor_count * 4
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().okpz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def philox(k0: int, k1: int, counters: np.ndarray) -> np.ndarray:

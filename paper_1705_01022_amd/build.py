@@ -1,4 +1,4 @@
-"""Build step for the HIP library: compiles ``csrc/okpz.hip`` for gfx950 into
+"""Build step for the HIP library: compiles ``csrc/*.hip`` for gfx950 into
 ``paper_1705_01022_amd/lib/libokpz.so`` with hipcc (cross-compiles without a GPU).
 
 Usage: ``python -m paper_1705_01022_amd.build`` (or ``__graft_entry__.build()``).
@@ -15,13 +15,13 @@ SRC_DIR = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libokpz.so")
 ARCH = "gfx950"
+SOURCES = ["okpz.hip", "batch.hip"]
 
-HIPCC_FLAGS = [
+COMPILE_FLAGS = [
     "-O3",
     "-std=c++17",
     "--offload-arch=" + ARCH,
     "-fPIC",
-    "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -37,16 +37,39 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the library."""
     os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp, os.path.join(SRC_DIR, "okpz.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building %s" % LIB)
-    os.replace(tmp, LIB)
+    tag = "%d" % os.getpid()
+    objs, procs = [], []
+    for f in SOURCES:
+        obj = os.path.join(LIB_DIR, "%s.%s.o" % (os.path.splitext(f)[0], tag))
+        cmd = [hipcc()] + COMPILE_FLAGS + ["-c", "-o", obj, os.path.join(SRC_DIR, f)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True), f))
+        objs.append(obj)
+    failed = []
+    for proc, f in procs:
+        out, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(f)
+    try:
+        if failed:
+            raise RuntimeError("hipcc failed compiling %s" % ", ".join(failed))
+        tmp = LIB + ".tmp" + tag
+        cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking %s" % LIB)
+        os.replace(tmp, LIB)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     return LIB
 
 

@@ -1,0 +1,701 @@
+// Batched execution: many independent lattices (realisations of any size)
+// advanced by one persistent kernel launch.
+//
+// Work items are (lattice, generation g = 4 * MCS-in-launch + step, tile).
+// They are numbered generation-major and handed out in that order through a
+// global ticket counter; an item of lattice r and generation g may start once
+// all g * tiles(r) items of r's earlier generations have finished (the same
+// device-wide step order a per-step launch gives, Sec. 3.1, but per lattice,
+// so the steps of different lattices overlap).  An item only ever waits for
+// items with smaller tickets, which are held by running workgroups, so the
+// queue always drains; every wait is also bounded in time and a timed-out
+// wait stops the whole launch with an error flag.
+//
+// Lattices are ordered by their MCS count of the launch (descending), so the
+// lattices taking part in generation g are always a prefix of that order; the
+// item numbering is described by a few "phases" of constant prefix length.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace okpz;
+using namespace okpz_host;
+
+namespace {
+
+struct BatchSlot {
+    StepArgs a;            // lattice constants; ox, oy, set, c3 are filled per item
+    uint32_t accept;       // lane draws carry acceptance variates
+    uint32_t ntiles;       // tiles per device step
+    uint32_t origin_mode;  // OKPZ_ORIGIN_*
+    uint32_t n_mcs;        // MCS of this launch
+};
+
+struct BatchPhase {
+    uint64_t first_item;     // ticket of the phase's first item
+    uint32_t gen_begin;      // first generation of the phase
+    uint32_t nslots;         // lattices taking part: the first nslots of the table
+    uint32_t items_per_gen;  // tiles of those lattices
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const BatchSlot *slots;
+    const uint32_t *tile_prefix;  // tile_prefix[i] = tiles of lattices 0 .. i-1
+    const BatchPhase *phases;     // nphase phases, then a sentinel with first_item = total
+    uint32_t nphase;
+    uint64_t total_items;
+    const uint64_t *mcs_base;  // MCS count of each lattice at the launch
+    uint32_t *done;            // finished items per lattice (zeroed before the launch)
+    unsigned long long *ticket;
+    uint32_t *error;      // sticky: set when a dependency wait timed out
+    uint64_t wait_ticks;  // wait limit in wall-clock ticks
+};
+
+// Element k of permutation number `pick` (lexicographic order) of {0,1,2,3}.
+__device__ __forceinline__ uint32_t perm_element(uint32_t pick, uint32_t k)
+{
+    uint32_t avail = 0x3210u;  // remaining elements, 4 bits each, ascending
+    const uint32_t digit[4] = {pick / 6u, (pick % 6u) / 2u, pick % 2u, 0u};
+    uint32_t e = 0;
+    for (uint32_t i = 0; i <= k; ++i) {
+        const uint32_t sh = 4u * digit[i];
+        e = (avail >> sh) & 0xFu;
+        const uint32_t low = avail & ((1u << sh) - 1u);
+        avail = low | ((avail >> (sh + 4u)) << sh);
+    }
+    return e;
+}
+
+template <int SCHEME, int CPT>
+__global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t cmd[4];  // lattice, tile, generation, stop
+    const uint32_t tid = threadIdx.x;
+    uint32_t my_slot = 0;
+    for (;;) {
+        if (tid == 0) {
+            uint32_t r = 0, t = 0, g = 0, stop = 0;
+            const unsigned long long i = atomicAdd(B.ticket, 1ull);
+            if (i >= B.total_items || __hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                stop = 1;
+            } else {
+                uint32_t lo = 0, hi = B.nphase;
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (B.phases[mid].first_item <= i) lo = mid; else hi = mid;
+                }
+                const BatchPhase ph = B.phases[lo];
+                const uint64_t rel = i - ph.first_item;
+                g = ph.gen_begin + (uint32_t)(rel / ph.items_per_gen);
+                const uint32_t off = (uint32_t)(rel % ph.items_per_gen);
+                lo = 0;
+                hi = ph.nslots;
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (B.tile_prefix[mid] <= off) lo = mid; else hi = mid;
+                }
+                r = lo;
+                t = off - B.tile_prefix[r];
+                const uint32_t need = g * B.slots[r].ntiles;
+                if (need > 0u) {
+                    const uint64_t t0 = wall_clock64();
+                    while (__hip_atomic_load(&B.done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (__hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            stop = 1;
+                            break;
+                        }
+                        if (wall_clock64() - t0 > B.wait_ticks) {
+                            atomicOr(B.error, 1u);
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            cmd[0] = r;
+            cmd[1] = t;
+            cmd[2] = g;
+            cmd[3] = stop;
+            my_slot = r;
+        }
+        __syncthreads();
+        if (cmd[3]) break;
+        const uint32_t r = __builtin_amdgcn_readfirstlane(cmd[0]);
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(cmd[1]);
+        const uint32_t g = __builtin_amdgcn_readfirstlane(cmd[2]);
+        const BatchSlot &S = B.slots[r];
+        StepArgs A = S.a;
+        // MCS draw of the lattice's MCS m (as on the host): origin and set order
+        const uint64_t m = B.mcs_base[r] + (g >> 2);
+        const uint32_t k = g & 3u;
+        const u32x4 w = philox4x32_10(A.key0, A.key1, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)(m << 2));
+        uint32_t ox = w.x & A.L_mask, oy = w.y & A.L_mask;
+        if (S.origin_mode == OKPZ_ORIGIN_FIXED) ox = oy = 0u;
+        if (S.origin_mode == OKPZ_ORIGIN_COARSE) {
+            ox &= ~3u;
+            oy &= ~3u;
+        }
+        const uint32_t set = perm_element((uint32_t)(((uint64_t)w.z * 24u) >> 32), k);
+        A.ox = ox;
+        A.oy = oy;
+        A.set_a = set & 1u;
+        A.set_b = set >> 1;
+        A.c3 = (uint32_t)(m << 2) | k;
+        // the earlier steps' words, written by other workgroups, become visible
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (S.accept)
+            sweep_tile<SCHEME, true, CPT>(A, smem, tile);
+        else
+            sweep_tile<SCHEME, false, CPT>(A, smem, tile);
+        // publish this tile's words before counting the item as done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(&B.done[my_slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void batch_reset_kernel(uint32_t *done, uint32_t n, unsigned long long *ticket)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    if (threadIdx.x == 0) *ticket = 0ull;
+}
+
+__global__ void batch_advance_kernel(uint64_t *mcs, const BatchSlot *slots, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) mcs[i] += slots[i].n_mcs;
+}
+
+constexpr uint64_t kWaitSeconds = 20;  // far above any single tile's sweep
+constexpr uint32_t kStaticLds = 64;    // batch_kernel's static LDS, rounded up
+
+}  // namespace
+
+struct okpz_batch {
+    hipStream_t stream = nullptr;
+    std::vector<okpz_lattice *> slots;  // nullptr: free slot
+    int32_t scheme = -1;                // block scheme shared by all members
+    // configuration (physical mapping only)
+    uint32_t threads = 0;  // 0: 256
+    uint32_t grid = 0;     // 0: as many workgroups as fit on the device at once
+    bool use_graph = true;
+    // device tables
+    BatchSlot *d_slots = nullptr;
+    uint32_t *d_prefix = nullptr;
+    BatchPhase *d_phases = nullptr;
+    uint64_t *d_mcs = nullptr;
+    uint32_t *d_done = nullptr;
+    unsigned long long *d_ticket = nullptr;
+    uint32_t *d_error = nullptr;
+    size_t cap_slots = 0, cap_phases = 0;
+    // pinned staging for the tables (rewritten only after a stream sync)
+    uint8_t *h_stage = nullptr;
+    size_t stage_cap = 0;
+    uint32_t *h_error = nullptr;
+    // what the device tables hold
+    std::vector<uint8_t> key;        // tables + launch shape of the captured graph
+    std::vector<int32_t> table_slot; // table index -> slot
+    std::vector<uint64_t> dev_mcs;   // per table index: MCS count the device holds
+    hipGraphExec_t gexec = nullptr;
+    bool failed = false;
+    // timing
+    bool timing = false;
+    std::vector<TimedPair> pairs;
+    uint64_t launches = 0;
+    uint64_t attempts = 0;
+};
+
+namespace {
+
+void batch_release(okpz_batch *b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (auto &tp : b->pairs) {
+        (void)hipEventDestroy(tp.start);
+        (void)hipEventDestroy(tp.stop);
+    }
+    (void)hipFree(b->d_slots);
+    (void)hipFree(b->d_prefix);
+    (void)hipFree(b->d_phases);
+    (void)hipFree(b->d_mcs);
+    (void)hipFree(b->d_done);
+    (void)hipFree(b->d_ticket);
+    (void)hipFree(b->d_error);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->h_error) (void)hipHostFree(b->h_error);
+    delete b;
+}
+
+int grow_tables(okpz_batch *b, size_t nslots, size_t nphases)
+{
+    if (nslots > b->cap_slots) {
+        const size_t cap = std::max<size_t>(nslots, 2 * b->cap_slots);
+        (void)hipFree(b->d_slots);
+        (void)hipFree(b->d_prefix);
+        (void)hipFree(b->d_mcs);
+        (void)hipFree(b->d_done);
+        b->d_slots = nullptr;
+        b->d_prefix = nullptr;
+        b->d_mcs = nullptr;
+        b->d_done = nullptr;
+        b->cap_slots = 0;
+        if (hipMalloc(&b->d_slots, cap * sizeof(BatchSlot)) != hipSuccess ||
+            hipMalloc(&b->d_prefix, (cap + 1) * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&b->d_mcs, cap * sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc(&b->d_done, cap * sizeof(uint32_t)) != hipSuccess)
+            return OKPZ_ENOMEM;
+        b->cap_slots = cap;
+    }
+    if (nphases + 1 > b->cap_phases) {
+        const size_t cap = std::max<size_t>(nphases + 1, 2 * b->cap_phases);
+        (void)hipFree(b->d_phases);
+        b->d_phases = nullptr;
+        b->cap_phases = 0;
+        if (hipMalloc(&b->d_phases, cap * sizeof(BatchPhase)) != hipSuccess) return OKPZ_ENOMEM;
+        b->cap_phases = cap;
+    }
+    const size_t need = b->cap_slots * (sizeof(BatchSlot) + sizeof(uint32_t) + sizeof(uint64_t)) + sizeof(uint32_t) +
+                        8 + b->cap_phases * sizeof(BatchPhase);
+    if (need > b->stage_cap) {
+        if (b->h_stage) (void)hipHostFree(b->h_stage);
+        b->h_stage = nullptr;
+        b->stage_cap = 0;
+        if (hipHostMalloc(&b->h_stage, need, hipHostMallocDefault) != hipSuccess) return OKPZ_ENOMEM;
+        b->stage_cap = need;
+    }
+    return OKPZ_OK;
+}
+
+template <int SCHEME, int CPT>
+const void *batch_fn()
+{
+    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT>);
+}
+
+const void *batch_kernel_for(int scheme, uint32_t cpt)
+{
+#define OKPZ_BATCH_CASES(S)                          \
+    switch (cpt) {                                   \
+    case 1: return batch_fn<S, 1>();                 \
+    case 2: return batch_fn<S, 2>();                 \
+    case 4: return batch_fn<S, 4>();                 \
+    case 8: return batch_fn<S, 8>();                 \
+    case 16: return batch_fn<S, 16>();               \
+    default: return nullptr;                         \
+    }
+    switch (scheme) {
+    case kDT: OKPZ_BATCH_CASES(kDT)
+    case kDB: OKPZ_BATCH_CASES(kDB)
+    case kDTR: OKPZ_BATCH_CASES(kDTR)
+    default: return nullptr;
+    }
+#undef OKPZ_BATCH_CASES
+}
+
+// The launches of one batch run, in stream order: reset counters, the
+// persistent kernel, advance the per-lattice MCS counts.
+struct LaunchPlan {
+    const void *fn;
+    uint32_t threads, grid, nslots;
+    size_t lds;
+    BatchArgs args;
+};
+
+int enqueue(okpz_batch *b, const LaunchPlan &lp)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, b->stream, b->d_done, lp.nslots, b->d_ticket);
+    void *kargs[] = {const_cast<BatchArgs *>(&lp.args)};
+    HIP_TRY(hipLaunchKernel(lp.fn, dim3(lp.grid), dim3(lp.threads), kargs, lp.lds, b->stream));
+    hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, b->stream, b->d_mcs, b->d_slots, lp.nslots);
+    HIP_TRY(hipGetLastError());
+    return OKPZ_OK;
+}
+
+int batch_check_error(okpz_batch *b)
+{
+    HIP_TRY(hipMemcpyAsync(b->h_error, b->d_error, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (*b->h_error) b->failed = true;
+    return b->failed ? OKPZ_EWAIT : OKPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int okpz_batch_create(void *hip_stream, okpz_batch **out)
+{
+    if (!out) return OKPZ_EINVAL;
+    *out = nullptr;
+    okpz_batch *b = new (std::nothrow) okpz_batch();
+    if (!b) return OKPZ_ENOMEM;
+    b->stream = (hipStream_t)hip_stream;
+    b->use_graph = hip_stream != nullptr;  // the null stream cannot be captured
+    if (hipMalloc(&b->d_ticket, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&b->d_error, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&b->h_error, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        batch_release(b);
+        return OKPZ_ENOMEM;
+    }
+    *b->h_error = 0;
+    if (hipMemcpyAsync(b->d_error, b->h_error, sizeof(uint32_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        batch_release(b);
+        return OKPZ_EHIP;
+    }
+    *out = b;
+    return OKPZ_OK;
+}
+
+int okpz_batch_destroy(okpz_batch *b)
+{
+    if (!b) return OKPZ_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    return OKPZ_OK;
+}
+
+int okpz_batch_add(okpz_batch *b, okpz_lattice *lat, int32_t *slot)
+{
+    if (!b || !lat || !slot) return OKPZ_EINVAL;
+    if (lat->stream != b->stream) return OKPZ_EINVAL;
+    if (b->scheme >= 0 && lat->prm.block_scheme != b->scheme) return OKPZ_EINVAL;
+    for (okpz_lattice *m : b->slots)
+        if (m == lat) return OKPZ_EINVAL;
+    int32_t s = -1;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (!b->slots[i]) {
+            s = (int32_t)i;
+            break;
+        }
+    if (s < 0) {
+        s = (int32_t)b->slots.size();
+        b->slots.push_back(nullptr);
+    }
+    b->slots[s] = lat;
+    b->scheme = lat->prm.block_scheme;
+    *slot = s;
+    return OKPZ_OK;
+}
+
+int okpz_batch_remove(okpz_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || (size_t)slot >= b->slots.size() || !b->slots[slot]) return OKPZ_EINVAL;
+    // the lattice may be destroyed right after: finish what uses it
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->slots[slot] = nullptr;
+    bool any = false;
+    for (okpz_lattice *m : b->slots) any |= m != nullptr;
+    if (!any) b->scheme = -1;
+    while (!b->slots.empty() && !b->slots.back()) b->slots.pop_back();
+    b->key.clear();  // tables refer to the removed lattice
+    return OKPZ_OK;
+}
+
+int okpz_batch_size(const okpz_batch *b, uint32_t *nslots)
+{
+    if (!b || !nslots) return OKPZ_EINVAL;
+    *nslots = (uint32_t)b->slots.size();
+    return OKPZ_OK;
+}
+
+int okpz_batch_config(okpz_batch *b, uint32_t threads, uint32_t grid, int use_graph)
+{
+    if (!b) return OKPZ_EINVAL;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256) return OKPZ_EINVAL;
+    if (use_graph && !b->stream) return OKPZ_EINVAL;
+    b->threads = threads;
+    b->grid = grid;
+    b->use_graph = use_graph != 0;
+    b->key.clear();
+    return OKPZ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One persistent launch (reset, batch kernel, advance) for the members with
+// n_mcs[s] > 0, already validated; 4 * n_mcs * tiles < 2^31 for each.
+int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const double *q)
+{
+    const size_t ns = b->slots.size();
+    std::vector<int32_t> order;
+    for (size_t s = 0; s < ns; ++s)
+        if (n_mcs[s] > 0) order.push_back((int32_t)s);
+    if (order.empty()) return OKPZ_OK;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return n_mcs[a] > n_mcs[c]; });
+    const uint32_t n = (uint32_t)order.size();
+
+    // launch shape: lanes per workgroup, cells per lane (largest domain)
+    const uint32_t nt = b->threads ? b->threads : 256u;
+    uint32_t max_cells = 1;
+    for (int32_t s : order) max_cells = std::max(max_cells, cells_of(b->slots[s]->prm));
+    uint32_t cpt = 1;
+    while (cpt * nt < max_cells) cpt *= 2;
+    if (cpt > 16) return OKPZ_EINVAL;
+
+    // tables
+    std::vector<BatchSlot> slots(n);
+    std::vector<uint32_t> prefix(n + 1, 0);
+    size_t lds = 0;
+    uint64_t attempts = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        okpz_lattice *lat = b->slots[order[i]];
+        const okpz_params &prm = lat->prm;
+        const double pd = p[order[i]], qr = q[order[i]];
+        const LaneShape ls = lane_shape(prm, pd, qr);
+        BatchSlot &S = slots[i];
+        std::memset(&S, 0, sizeof(S));
+        S.a = base_args(lat, ls, pd, qr);
+        S.accept = ls.accept ? 1u : 0u;
+        S.ntiles = (prm.L / (2 * prm.dom_x)) * (prm.L / (2 * prm.dom_y));
+        S.origin_mode = (uint32_t)prm.origin_mode;
+        S.n_mcs = (uint32_t)n_mcs[order[i]];
+        prefix[i + 1] = prefix[i] + S.ntiles;
+        lds = std::max<size_t>(lds, step_lds_bytes(prm, nt * cpt));
+        attempts += (uint64_t)prm.L * prm.L * S.n_mcs;
+    }
+    // the kernel's own 16 bytes of static LDS come on top
+    if (lds > kMaxLds - kStaticLds) return OKPZ_EINVAL;
+    std::vector<BatchPhase> phases;
+    uint64_t total = 0;
+    {
+        uint32_t gen = 0;
+        uint32_t count = n;
+        while (count > 0) {
+            const uint32_t gen_end = 4u * slots[count - 1].n_mcs;
+            if (gen_end > gen) {
+                BatchPhase ph;
+                ph.first_item = total;
+                ph.gen_begin = gen;
+                ph.nslots = count;
+                ph.items_per_gen = prefix[count];
+                ph.pad = 0;
+                phases.push_back(ph);
+                total += (uint64_t)(gen_end - gen) * prefix[count];
+                gen = gen_end;
+            }
+            --count;
+        }
+        BatchPhase end;
+        std::memset(&end, 0, sizeof(end));
+        end.first_item = total;
+        phases.push_back(end);
+    }
+    const uint32_t nphase = (uint32_t)phases.size() - 1;
+
+    const void *fn = batch_kernel_for(b->scheme, cpt);
+    if (!fn) return OKPZ_EINVAL;
+    if (lds > 64u * 1024u)
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLds - kStaticLds)));
+    uint32_t grid = b->grid;
+    if (grid == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)nt, lds));
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        grid = (uint32_t)std::max(1, per_cu * cus);
+    }
+    grid = (uint32_t)std::min<uint64_t>(grid, total);
+
+    // identity of the tables and the launch shape: an unchanged key replays the graph
+    std::vector<uint8_t> key(sizeof(BatchSlot) * n + sizeof(uint32_t) * (n + 1) + sizeof(BatchPhase) * phases.size() +
+                             4 * sizeof(uint32_t));
+    {
+        uint8_t *k = key.data();
+        std::memcpy(k, slots.data(), sizeof(BatchSlot) * n);
+        k += sizeof(BatchSlot) * n;
+        std::memcpy(k, prefix.data(), sizeof(uint32_t) * (n + 1));
+        k += sizeof(uint32_t) * (n + 1);
+        std::memcpy(k, phases.data(), sizeof(BatchPhase) * phases.size());
+        k += sizeof(BatchPhase) * phases.size();
+        const uint32_t shape[4] = {nt, cpt, grid, b->use_graph ? 1u : 0u};
+        std::memcpy(k, shape, sizeof(shape));
+    }
+    std::vector<int32_t> table_slot(order.begin(), order.end());
+    const bool same_tables = key == b->key && table_slot == b->table_slot;
+    bool mcs_current = same_tables;
+    if (same_tables)
+        for (uint32_t i = 0; i < n; ++i) mcs_current &= b->dev_mcs[i] == b->slots[order[i]]->mcs;
+
+    if (!same_tables || !mcs_current) {
+        HIP_TRY(hipStreamSynchronize(b->stream));  // the staging buffer may still be read
+        const int rc = grow_tables(b, n, phases.size());
+        if (rc != OKPZ_OK) return rc;
+        uint8_t *st = b->h_stage;
+        BatchSlot *hs = reinterpret_cast<BatchSlot *>(st);
+        std::memcpy(hs, slots.data(), sizeof(BatchSlot) * n);
+        uint64_t *hm = reinterpret_cast<uint64_t *>(hs + n);
+        for (uint32_t i = 0; i < n; ++i) hm[i] = b->slots[order[i]]->mcs;
+        uint32_t *hp = reinterpret_cast<uint32_t *>(hm + n);
+        std::memcpy(hp, prefix.data(), sizeof(uint32_t) * (n + 1));
+        BatchPhase *hph = reinterpret_cast<BatchPhase *>(
+            reinterpret_cast<uint8_t *>(hp) + ((sizeof(uint32_t) * (n + 1) + 7) & ~size_t(7)));
+        std::memcpy(hph, phases.data(), sizeof(BatchPhase) * phases.size());
+        HIP_TRY(hipMemcpyAsync(b->d_slots, hs, sizeof(BatchSlot) * n, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_mcs, hm, sizeof(uint64_t) * n, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_prefix, hp, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_phases, hph, sizeof(BatchPhase) * phases.size(), hipMemcpyHostToDevice,
+                               b->stream));
+        b->dev_mcs.assign(n, 0);
+        for (uint32_t i = 0; i < n; ++i) b->dev_mcs[i] = b->slots[order[i]]->mcs;
+    }
+
+    LaunchPlan lp;
+    lp.fn = fn;
+    lp.threads = nt;
+    lp.grid = grid;
+    lp.nslots = n;
+    lp.lds = lds;
+    lp.args.slots = b->d_slots;
+    lp.args.tile_prefix = b->d_prefix;
+    lp.args.phases = b->d_phases;
+    lp.args.nphase = nphase;
+    lp.args.total_items = total;
+    lp.args.mcs_base = b->d_mcs;
+    lp.args.done = b->d_done;
+    lp.args.ticket = b->d_ticket;
+    lp.args.error = b->d_error;
+    {
+        int dev = 0, khz = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        lp.args.wait_ticks = (uint64_t)std::max(khz, 1) * 1000ull * kWaitSeconds;
+    }
+
+    TimedPair tp;
+    tp.kind = 0;
+    if (b->timing) {
+        HIP_TRY(hipEventCreate(&tp.start));
+        HIP_TRY(hipEventCreate(&tp.stop));
+        HIP_TRY(hipEventRecord(tp.start, b->stream));
+    }
+    if (b->use_graph) {
+        if (!same_tables || !b->gexec) {
+            if (b->gexec) {
+                (void)hipGraphExecDestroy(b->gexec);
+                b->gexec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue(b, lp);
+            const hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+            if (rc != OKPZ_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+            const hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                b->gexec = nullptr;
+                return hip_fail(ei, "hipGraphInstantiate");
+            }
+        }
+        HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+    } else {
+        const int rc = enqueue(b, lp);
+        if (rc != OKPZ_OK) return rc;
+    }
+    if (b->timing) {
+        HIP_TRY(hipEventRecord(tp.stop, b->stream));
+        b->pairs.push_back(tp);
+    }
+    b->key.swap(key);
+    b->table_slot.swap(table_slot);
+    for (uint32_t i = 0; i < n; ++i) {
+        okpz_lattice *lat = b->slots[order[i]];
+        lat->mcs += slots[i].n_mcs;
+        b->dev_mcs[i] = lat->mcs;
+    }
+    b->launches += 1;
+    b->attempts += attempts;
+    return OKPZ_OK;
+}
+
+uint64_t tiles_of(const okpz_params &prm) { return (uint64_t)(prm.L / (2 * prm.dom_x)) * (prm.L / (2 * prm.dom_y)); }
+
+}  // namespace
+
+extern "C" {
+
+int okpz_batch_run(okpz_batch *b, const uint64_t *n_mcs, const double *p, const double *q)
+{
+    if (!b || !n_mcs || !p || !q) return OKPZ_EINVAL;
+    if (b->failed) return OKPZ_EWAIT;
+    const size_t ns = b->slots.size();
+    // validate everything before anything is launched
+    uint64_t max_n = 0;
+    for (size_t s = 0; s < ns; ++s) {
+        if (n_mcs[s] == 0) continue;
+        okpz_lattice *lat = b->slots[s];
+        if (!lat) return OKPZ_EINVAL;
+        if (!(p[s] >= 0.0 && p[s] <= 1.0 && q[s] >= 0.0 && q[s] <= 1.0)) return OKPZ_EINVAL;
+        if (n_mcs[s] > kMcsLimit || lat->mcs + n_mcs[s] > kMcsLimit) return OKPZ_EOVERFLOW;
+        max_n = std::max(max_n, n_mcs[s]);
+    }
+    // launches of at most `chunk` MCS per lattice keep the per-lattice item
+    // counters below 2^31
+    uint64_t chunk = max_n;
+    for (size_t s = 0; s < ns; ++s)
+        if (n_mcs[s] > 0) chunk = std::min<uint64_t>(chunk, ((uint64_t(1) << 31) - 1) / (4 * tiles_of(b->slots[s]->prm)));
+    std::vector<uint64_t> left(n_mcs, n_mcs + ns), part(ns);
+    while (max_n > 0) {
+        for (size_t s = 0; s < ns; ++s) part[s] = std::min(left[s], chunk);
+        const int rc = batch_run_once(b, part.data(), p, q);
+        if (rc != OKPZ_OK) return rc;
+        max_n = 0;
+        for (size_t s = 0; s < ns; ++s) {
+            left[s] -= part[s];
+            max_n = std::max(max_n, left[s]);
+        }
+    }
+    return OKPZ_OK;
+}
+
+int okpz_batch_sync(okpz_batch *b)
+{
+    if (!b) return OKPZ_EINVAL;
+    return batch_check_error(b);
+}
+
+int okpz_batch_timing(okpz_batch *b, int enable)
+{
+    if (!b) return OKPZ_EINVAL;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (auto &tp : b->pairs) {
+        (void)hipEventDestroy(tp.start);
+        (void)hipEventDestroy(tp.stop);
+    }
+    b->pairs.clear();
+    b->timing = enable != 0;
+    b->launches = 0;
+    b->attempts = 0;
+    return OKPZ_OK;
+}
+
+int okpz_batch_get_timing(okpz_batch *b, double *ms, uint64_t *launches, uint64_t *attempts)
+{
+    if (!b) return OKPZ_EINVAL;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    double total = 0;
+    for (auto &tp : b->pairs) {
+        float e = 0;
+        HIP_TRY(hipEventElapsedTime(&e, tp.start, tp.stop));
+        total += e;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = b->launches;
+    if (attempts) *attempts = b->attempts;
+    return OKPZ_OK;
+}
+
+}  // extern "C"

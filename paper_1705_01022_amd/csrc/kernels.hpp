@@ -27,7 +27,7 @@ enum : int { kDT = 0, kDB = 1, kDTR = 2 };
 // ---------------------------------------------------------------- init
 // Flat state: word i of the lattice belongs to row i % 4 of its block, so
 // its parity is that of i.
-__global__ void fill_flat_kernel(uint32_t *__restrict__ words, uint64_t n)
+static __global__ void fill_flat_kernel(uint32_t *__restrict__ words, uint64_t n)
 {
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -35,7 +35,7 @@ __global__ void fill_flat_kernel(uint32_t *__restrict__ words, uint64_t n)
 }
 
 // ---------------------------------------------------------------- Philox test
-__global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ctr,
+static __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ctr,
                               uint32_t *__restrict__ out, uint64_t n)
 {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -281,17 +281,17 @@ template <bool ACCEPT, int CPT>
 __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint32_t *cpos, uint32_t *flags,
                                          const CellGeom (&g)[CPT], uint32_t (&rw)[CPT][4], BlockDraw &bd,
                                          Draw (&cur)[CPT], Draw (&nxt)[CPT], uint32_t rho, uint32_t tile,
-                                         uint32_t offx, uint32_t offy, bool active_lane)
+                                         uint32_t offx, uint32_t offy, const bool (&act)[CPT])
 {
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     if (rho + 1u < A.rounds) {
         const uint32_t f16 = next_block_field(A, bd, rho + 1u, tile);
-        const uint32_t nbuf = ((rho + 1u) & 1u) * A.ncell;
+        const uint32_t nbuf = ((rho + 1u) & 1u) * (NT * CPT);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const uint32_t field = next_field(A, rw[j], rho + 1u, tid * CPT + j, tile);
             nxt[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
-            if (CPT > 1 || active_lane) cpos[nbuf + j * NT + tid] = nxt[j].pos;
+            if (act[j]) cpos[nbuf + j * NT + tid] = nxt[j].pos;
         }
 #pragma unroll
         for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, nxt[j], rho + 1u, tid * CPT + j, tile);
@@ -299,7 +299,7 @@ __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint3
     // A rim attempt waits if the neighbouring cell's attempt sits on the site
     // to its right (right column / corner) or below it (bottom row / corner).
     // A target one past the domain edge is never a published site.
-    const uint32_t buf = (rho & 1u) * A.ncell;
+    const uint32_t buf = (rho & 1u) * (NT * CPT);
     bool def[CPT];
     bool any1 = false, any2 = false;
 #pragma unroll
@@ -307,12 +307,12 @@ __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint3
         const uint32_t pr = cpos[buf + (g[j].nb & 0xFFFFu)], pd = cpos[buf + (g[j].nb >> 16)];
         const uint32_t want_r = (cur[j].rim & 1u) ? cur[j].pos + 1u : 0xFFFFFFFFu;
         const uint32_t want_d = (cur[j].rim & 2u) ? cur[j].pos + 0x10000u : 0xFFFFFFFFu;
-        def[j] = (CPT > 1 || active_lane) && (pr == want_r || pd == want_d);
+        def[j] = act[j] && (pr == want_r || pd == want_d);
         any1 |= def[j] && cur[j].rim != 3u;
         any2 |= def[j] && cur[j].rim == 3u;
     }
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, cur[j], !def[j] && (CPT > 1 || active_lane));
+    for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, cur[j], !def[j] && act[j]);
     const uint64_t b1 = __ballot(any1), b2 = __ballot(any2);
     if ((tid & 63u) == 0u && (b1 | b2)) atomicOr(&flags[rho % 3u], (b1 ? 1u : 0u) | (b2 ? 2u : 0u));
     if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
@@ -332,19 +332,22 @@ __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint3
     }
 }
 
-// LDS words of one device-step workgroup (see step_kernel).
+// LDS words of one device-step workgroup (see sweep_tile); nslot = lanes x
+// cells per lane.
 __host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint32_t NWX, uint32_t PY, uint32_t NB,
-                                                   uint32_t shared_edges, uint32_t ncell, bool db)
+                                                   uint32_t shared_edges, uint32_t nslot, bool db)
 {
-    return NR * P + (NWX + 1u) * PY + (shared_edges ? 16u * NB : 0u) + (db ? 2u * ncell + 4u : 0u);
+    return NR * P + (NWX + 1u) * PY + (shared_edges ? 16u * NB : 0u) + (db ? 2u * nslot + 4u : 0u);
 }
 
-// One device step.  Workgroup = one tile; its active domain (sub-tile set
-// (set_a, set_b)) is staged with its +x column and +y row in LDS, swept by
-// Cx*Cy single-hit rounds (every cell gets exactly one attempt per round,
-// Sec. 3.1) and written back.  Same-set domains of at least 32 sites never
-// share a block, so their write-back is plain; narrower ones XOR their
-// changes into the two edge blocks of each band.
+// One domain sweep (device step of one tile).  The tile's active domain
+// (sub-tile set (set_a, set_b)) is staged with its +x column and +y row in
+// LDS, swept by Cx*Cy single-hit rounds (every cell gets exactly one attempt
+// per round, Sec. 3.1) and written back.  Same-set domains of at least 32
+// sites never share a block, so their write-back is plain; narrower ones XOR
+// their changes into the two edge blocks of each band.  Lane `tid` owns cells
+// tid*CPT .. tid*CPT+CPT-1; cells at or past A.ncell are idle (a domain with
+// fewer cells than the workgroup has slots).
 //
 // DT / DTr: the attempts of one round never touch each other, so a round is
 // one pass.  DB (delayed borders: bulk attempts first, then those on the
@@ -358,15 +361,14 @@ __host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint
 // on the random stream, so each cell publishes its next round's site one
 // round ahead (double-buffered in LDS) and the check needs no extra barrier.
 template <int SCHEME, bool ACCEPT, int CPT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs A)
+__device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, uint32_t tile)
 {
-    extern __shared__ uint32_t smem[];
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
     uint32_t *lds = smem;                                              // sx plane, then sy plane
     uint32_t *orig = smem + A.NR * A.P + (A.NWX + 1u) * A.PY;          // edge blocks as loaded
-    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // DB: 2 x ncell published sites
-    uint32_t *flags = cpos + 2 * A.ncell;                              // DB: 3 round flags
+    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // DB: 2 x NT*CPT published sites
+    uint32_t *flags = cpos + 2u * NT * CPT;                            // DB: 3 round flags
 
-    const uint32_t tile = blockIdx.x;
     const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
     const uint32_t X0 = (A.ox + 2u * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
     const uint32_t Y0 = (A.oy + 2u * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
@@ -374,7 +376,6 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 
     copy_window<true>(A, lds, orig, X0 >> 5, Y0 >> 2);
 
-    const uint32_t tid = threadIdx.x, NT = blockDim.x;
     const uint32_t ncx_mask = (1u << A.log2ncx) - 1u;
     const uint32_t ncy_mask = (A.ncell >> A.log2ncx) - 1u;
     // a cell's published-site slot: cell c of thread c / CPT is stored at
@@ -383,18 +384,19 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
     auto slot_of = [&](uint32_t c) { return (c % CPT) * NT + c / CPT; };
     CellGeom g[CPT];
     uint32_t rw[CPT][4];
+    bool act[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         // a thread's cells are horizontal neighbours, so the lanes of one
         // instruction hit different LDS words
         const uint32_t cell = tid * CPT + j;
         const uint32_t cx = cell & ncx_mask, cy = (cell >> A.log2ncx) & ncy_mask;
+        act[j] = cell < A.ncell;
         g[j].base = (cx << A.log2Cx) | ((cy << A.log2Cy) << 16);
         g[j].nb = slot_of((cy << A.log2ncx) | ((cx + 1u) & ncx_mask)) |
                   (slot_of((((cy + 1u) & ncy_mask) << A.log2ncx) | cx) << 16);
         rw[j][0] = rw[j][1] = rw[j][2] = rw[j][3] = 0u;
     }
-    const bool active_lane = tid * CPT < A.ncell;  // CPT = 1 workgroups may have idle lanes
     BlockDraw bd = {0u, 0u, 0u, 0u};
 
     if (SCHEME != kDB) {
@@ -410,7 +412,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 #pragma unroll
             for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, d[j], rho, tid * CPT + j, tile);
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, d[j], CPT > 1 || active_lane);
+            for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, d[j], act[j]);
             __syncthreads();
         }
     } else {
@@ -420,7 +422,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
         for (int j = 0; j < CPT; ++j) {
             const uint32_t field = next_field(A, rw[j], 0u, tid * CPT + j, tile);
             da[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
-            if (CPT > 1 || active_lane) cpos[j * NT + tid] = da[j].pos;
+            if (act[j]) cpos[j * NT + tid] = da[j].pos;
         }
 #pragma unroll
         for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, da[j], 0u, tid * CPT + j, tile);
@@ -428,11 +430,19 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
         __syncthreads();
         // Cx*Cy rounds, an even number: alternate the two draw buffers
         for (uint32_t rho = 0; rho < A.rounds; rho += 2) {
-            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, da, db, rho, tile, offx, offy, active_lane);
-            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, db, da, rho + 1u, tile, offx, offy, active_lane);
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, da, db, rho, tile, offx, offy, act);
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, db, da, rho + 1u, tile, offx, offy, act);
         }
     }
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
+}
+
+// One device step of a single lattice: one workgroup per tile.
+template <int SCHEME, bool ACCEPT, int CPT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs A)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_tile<SCHEME, ACCEPT, CPT>(A, smem, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- measurement
@@ -441,7 +451,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 
 // Column-0 anchors h(0,y): one workgroup; each thread owns a run of bands,
 // reads the sy words of block 0 of each band, and a block scan joins the runs.
-__global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
+static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
                                                        uint32_t nbx_log2, int32_t *__restrict__ h0)
 {
     __shared__ int32_t part[1024];
@@ -649,7 +659,7 @@ __device__ __forceinline__ void add_i128(uint64_t &lo, int64_t &hi, uint64_t blo
 }
 
 // Final exact reduction of the per-row partials into 128-bit totals.
-__global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__restrict__ partial, uint32_t nrows,
+static __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__restrict__ partial, uint32_t nrows,
                                                      int64_t *__restrict__ out)
 {
     __shared__ uint64_t lo_s[kMomentFields][256];

@@ -1,0 +1,146 @@
+"""Batched execution: many lattices advanced by one persistent launch.
+
+Every member must equal the oracle's DTr emulation of that lattice alone,
+bit for bit, whatever the membership, the per-member MCS counts and rates,
+the launch shape (threads, persistent grid, graph capture) and whether the
+launch is a graph replay.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+# (L, D, C, p, q, n_mcs): sizes from one 16-cell domain to 1024-cell domains,
+# acceptance draws or not, different MCS counts (different phases of the queue)
+MIX = [
+    (64, 16, 8, 1.0, 0.0, 3),
+    (128, 32, 8, 0.5, 0.5, 5),
+    (64, 8, 4, 0.95, 0.05, 2),
+    (128, 64, 8, 1.0, 0.0, 4),
+    (256, 128, 8, 0.7, 0.2, 1),
+    (64, 32, 2, 0.0, 1.0, 3),
+]
+
+
+class Mirror:
+    """The oracle's copy of one member."""
+
+    def __init__(self, orc, L, D, C, scheme, p, q, stream):
+        self.emu = orc.Emu(L=L, Dx=D, Dy=D, Cx=C, Cy=C, scheme=scheme, p=p, q=q, seed=7, stream=stream)
+        self.s = orc.init_flat(L)
+        self.m = 0
+
+    def run(self, n):
+        for _ in range(n):
+            self.emu.mcs(self.s, self.m)
+            self.m += 1
+
+
+def make_batch(okpz, orc, scheme, mix=MIX):
+    b = okpz.Batch()
+    lats, mirrors = [], []
+    for i, (L, D, C, p, q, n) in enumerate(mix):
+        lats.append(b.lattice(L, D, D, C, C, scheme, seed=7, stream=100 + i))
+        mirrors.append(Mirror(orc, L, D, C, scheme, p, q, 100 + i))
+    return b, lats, mirrors
+
+
+def run_both(b, lats, mirrors, mix, ns):
+    b.run([n for n in ns], [m[3] for m in mix], [m[4] for m in mix])
+    b.sync()
+    for lat, mir, n in zip(lats, mirrors, ns):
+        mir.run(n)
+        assert lat.mcs == mir.m
+        assert np.array_equal(lat.sites(), mir.s), (lat.L, mir.m)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2], ids=["DT", "DB", "DTr"])
+def test_batch_matches_oracle(okpz, orc, scheme):
+    b, lats, mirrors = make_batch(okpz, orc, scheme)
+    ns = [m[5] for m in MIX]
+    run_both(b, lats, mirrors, MIX, ns)          # first launch: capture
+    run_both(b, lats, mirrors, MIX, ns)          # same tables: graph replay
+    run_both(b, lats, mirrors, MIX, [1, 0, 2, 0, 1, 3])  # some members idle
+    b.close()
+
+
+@pytest.mark.parametrize("threads,grid,graph", [(64, 0, True), (128, 1, False), (256, 3, True), (256, 0, False)])
+def test_batch_launch_shape_does_not_change_results(okpz, orc, threads, grid, graph):
+    b, lats, mirrors = make_batch(okpz, orc, 1)
+    b.config(threads, grid, graph)
+    run_both(b, lats, mirrors, MIX, [2, 3, 1, 2, 1, 2])
+    run_both(b, lats, mirrors, MIX, [2, 3, 1, 2, 1, 2])
+    b.close()
+
+
+def test_batch_membership_and_outside_runs(okpz, orc):
+    b, lats, mirrors = make_batch(okpz, orc, 0, MIX[:4])
+    mix = MIX[:4]
+    run_both(b, lats, mirrors, mix, [1, 1, 1, 1])
+    # a member run alone between batch runs (the batch re-reads its MCS count)
+    lats[1].run(2, mix[1][3], mix[1][4])
+    mirrors[1].run(2)
+    run_both(b, lats, mirrors, mix, [1, 1, 1, 1])
+    # remove a member, add a new one into the freed slot
+    b.remove(lats[2].slot)
+    assert b.size == 4
+    newlat = b.lattice(128, 16, 16, 8, 8, 0, seed=7, stream=300)
+    assert newlat.slot == 2
+    newmir = Mirror(orc, 128, 16, 8, 0, 1.0, 0.0, 300)
+    mix2 = [mix[0], mix[1], (128, 16, 8, 1.0, 0.0, 1), mix[3]]
+    lats2 = [lats[0], lats[1], newlat, lats[3]]
+    mirrors2 = [mirrors[0], mirrors[1], newmir, mirrors[3]]
+    run_both(b, lats2, mirrors2, mix2, [2, 1, 3, 1])
+    # the removed lattice still works on its own
+    lats[2].run(1, mix[2][3], mix[2][4])
+    mirrors[2].run(1)
+    assert np.array_equal(lats[2].sites(), mirrors[2].s)
+    # measurement of a member after batch runs
+    mo = lats[0].measure()
+    assert mo["w2"] == orc.w2(mirrors[0].s)
+    b.close()
+
+
+def test_batch_equals_plain_runs(okpz):
+    """A slice of the batched workload (uneven L, D = min(256, L/2), (1,0) and
+    (1/2,1/2)): every member equals the same lattice run alone with okpz_run."""
+    from workloads import batched_composition
+
+    comp = batched_composition(n=24, seed=1)
+    b = okpz.Batch()
+    batched, alone = [], []
+    for c in comp:
+        batched.append(b.lattice(c.L, c.Dx, c.Dy, c.Cx, c.Cy, c.scheme, seed=1, stream=c.stream))
+        alone.append(okpz.Lattice(c.L, c.Dx, c.Dy, c.Cx, c.Cy, c.scheme, seed=1, stream=c.stream))
+    b.run([3] * len(comp), [c.p for c in comp], [c.q for c in comp])
+    b.run([2] * len(comp), [c.p for c in comp], [c.q for c in comp])
+    b.sync()
+    for lat, c in zip(alone, comp):
+        lat.run(5, c.p, c.q)
+    for x, y in zip(batched, alone):
+        assert x.mcs == y.mcs == 5
+        assert np.array_equal(x.words(), y.words())
+    b.close()
+
+
+def test_batch_rejects_bad_arguments(okpz):
+    b = okpz.Batch()
+    a = b.lattice(64, 16, 16, 8, 8, 0)
+    with pytest.raises(okpz.OkpzError):
+        b.add(a)                                   # already a member
+    other = okpz.Lattice(64, 16, 16, 8, 8, 0)      # null stream
+    with pytest.raises(okpz.OkpzError):
+        b.add(other)
+    with pytest.raises(okpz.OkpzError):
+        b.lattice(64, 16, 16, 8, 8, 1)             # another block scheme
+    with pytest.raises(okpz.OkpzError):
+        b.run([1], [1.5], [0.0])                   # p outside [0, 1]
+    with pytest.raises(okpz.OkpzError):
+        b.config(96, 0, True)
+    b.remove(a.slot)
+    with pytest.raises(okpz.OkpzError):
+        b.remove(a.slot)
+    assert b.size == 0
+    b.run([], [], [])                              # nothing to do
+    b.close()
+    other.close()
