@@ -100,6 +100,8 @@ def lib():
         _lib.orc_moments.restype = ctypes.c_int
         _lib.orc_cross.argtypes = [u8p, u8p, ctypes.c_uint32, i64p]
         _lib.orc_cross.restype = ctypes.c_int
+        _lib.orc_slope_overlap.argtypes = [u8p, u8p, ctypes.c_uint32]
+        _lib.orc_slope_overlap.restype = ctypes.c_int64
         _lib.orc_cfg_size.restype = ctypes.c_uint32
         if _lib.orc_cfg_size() != ctypes.sizeof(DtrCfg):
             raise RuntimeError("oracle config struct layout mismatch")
@@ -298,3 +300,16 @@ def c_h(st: np.ndarray, ss: np.ndarray) -> float:
     s1t = mt["s1_even"] + mt["s1_odd"]
     s1s = ms["s1_even"] + ms["s1_odd"]
     return float(Fraction(n * cross(st, ss) - s1t * s1s, n * n))
+
+
+def slope_overlap(st: np.ndarray, ss: np.ndarray) -> int:
+    """Number of slope variables (both directions, all sites) equal to 1 in both states."""
+    return int(lib().orc_slope_overlap(_u8(st), _u8(ss), st.shape[0]))
+
+
+def c_s(st: np.ndarray, ss: np.ndarray) -> float:
+    """Slope autocorrelation C_s(t,s) = <n_t n_s> - <n_t><n_s> over the 2 L^2
+    slope variables (Sec. 2.1), with <n> = 1/2 by particle conservation;
+    correctly rounded."""
+    n = 2 * st.shape[0] * st.shape[1]
+    return float(Fraction(slope_overlap(st, ss), n) - Fraction(1, 4))

@@ -28,7 +28,8 @@
  *      under the counter-based random-number contract described at
  *      dtr_lane_draw() below.  Optional window mode for sampled checks.
  *   5. Heights and exact integer moments for W^2 (Sec. 2.1, roughness
- *      definition) and the height autocorrelation C_h (Sec. 2.1).
+ *      definition), the height autocorrelation C_h and the slope
+ *      autocorrelation C_s (Sec. 2.1).
  *
  * Parity status: every function here is pinned by the CPU tests
  * (brute force over all 990 states of the 4x4 torus, the exact master
@@ -682,6 +683,24 @@ int orc_cross(const uint8_t *st, const uint8_t *ss, uint32_t L, int64_t out[2])
     free(ht); free(hs);
     put_i128(acc, out);
     return 0;
+}
+
+/*
+ * Slope (lattice-gas) overlap of two states: the number of slope variables,
+ * over both directions of every site, that are 1 in both,
+ * sum_r [sx_t sx_s + sy_t sy_s].  The slope autocorrelation (Sec. 2.1)
+ * C_s(t,s) = <n_t n_s> - <n_t><n_s> averages n over the 2 L^2 slope variables;
+ * particle conservation fixes <n> = 1/2 in every state, so
+ * C_s = overlap / (2 L^2) - 1/4.
+ */
+int64_t orc_slope_overlap(const uint8_t *st, const uint8_t *ss, uint32_t L)
+{
+    int64_t acc = 0;
+    for (size_t i = 0; i < (size_t)L * L; ++i) {
+        const uint8_t both = (uint8_t)(st[i] & ss[i]);
+        acc += (both & 1) + ((both >> 1) & 1);
+    }
+    return acc;
 }
 
 /* size of the config struct, so the Python side can check its layout */

@@ -151,9 +151,9 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
         // the earlier steps' words, written by other workgroups, become visible
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (S.accept)
-            sweep_tile<SCHEME, true, CPT>(A, smem, tile);
+            sweep_tile<SCHEME, true, CPT, false>(A, smem, tile);
         else
-            sweep_tile<SCHEME, false, CPT>(A, smem, tile);
+            sweep_tile<SCHEME, false, CPT, false>(A, smem, tile);
         // publish this tile's words before counting the item as done
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();

@@ -347,7 +347,8 @@ __host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint
 // sites never share a block, so their write-back is plain; narrower ones XOR
 // their changes into the two edge blocks of each band.  Lane `tid` owns cells
 // tid*CPT .. tid*CPT+CPT-1; cells at or past A.ncell are idle (a domain with
-// fewer cells than the workgroup has slots).
+// fewer cells than the workgroup has slots); FULL: the caller guarantees
+// ncell = lanes x CPT.
 //
 // DT / DTr: the attempts of one round never touch each other, so a round is
 // one pass.  DB (delayed borders: bulk attempts first, then those on the
@@ -360,7 +361,7 @@ __host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint
 // result equals bulk -> edges -> corners exactly.  Attempt sites depend only
 // on the random stream, so each cell publishes its next round's site one
 // round ahead (double-buffered in LDS) and the check needs no extra barrier.
-template <int SCHEME, bool ACCEPT, int CPT>
+template <int SCHEME, bool ACCEPT, int CPT, bool FULL>
 __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, uint32_t tile)
 {
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
@@ -391,7 +392,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
         // instruction hit different LDS words
         const uint32_t cell = tid * CPT + j;
         const uint32_t cx = cell & ncx_mask, cy = (cell >> A.log2ncx) & ncy_mask;
-        act[j] = cell < A.ncell;
+        act[j] = FULL || cell < A.ncell;
         g[j].base = (cx << A.log2Cx) | ((cy << A.log2Cy) << 16);
         g[j].nb = slot_of((cy << A.log2ncx) | ((cx + 1u) & ncx_mask)) |
                   (slot_of((((cy + 1u) & ncy_mask) << A.log2ncx) | cx) << 16);
@@ -437,12 +438,14 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
 }
 
-// One device step of a single lattice: one workgroup per tile.
+// One device step of a single lattice: one workgroup per tile.  With more
+// than one cell per lane the workgroup shape divides the domain's cells
+// exactly; one cell per lane may leave lanes idle.
 template <int SCHEME, bool ACCEPT, int CPT>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];
-    sweep_tile<SCHEME, ACCEPT, CPT>(A, smem, blockIdx.x);
+    sweep_tile<SCHEME, ACCEPT, CPT, (CPT > 1)>(A, smem, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- measurement

@@ -153,3 +153,33 @@ def test_autocorr_equal_times_is_w2(orc):
     for _ in range(3000):
         orc.attempt(s, int(rng.integers(0, L)), int(rng.integers(0, L)), True, False)
     assert orc.c_h(s, s) == orc.w2(s)
+
+
+def test_slope_autocorr_definition_on_all_states(orc, space):
+    """C_s (Sec. 2.1) from the oracle's overlap count equals the definition
+    <n_t n_s> - <n_t><n_s> evaluated on slopes derived from enumerated heights
+    (means taken from the data, not assumed), for every 4x4 state against
+    several references; every state has <n> = 1/2 and C_s(s,s) = 1/4."""
+    refs = [space.slopes[i] for i in (0, 17, 333, 640, 989)]
+    for s in space.slopes:
+        n_s = np.concatenate([(s & 1).ravel(), ((s >> 1) & 1).ravel()]).astype(np.int64)
+        assert n_s.mean() == 0.5
+        assert orc.c_s(s, s) == 0.25
+        for r in refs:
+            n_r = np.concatenate([(r & 1).ravel(), ((r >> 1) & 1).ravel()]).astype(np.int64)
+            want = (n_s * n_r).mean() - n_s.mean() * n_r.mean()
+            assert orc.c_s(s, r) == want == orc.c_s(r, s)
+
+
+def test_slope_autocorr_closed_forms(orc):
+    for L in (4, 16, 64):
+        f = orc.init_flat(L)
+        # the flat state of opposite phase has every slope reversed
+        g = (f ^ 3).astype(np.uint8)
+        assert orc.check_state(g) == 0
+        assert orc.c_s(f, g) == -0.25
+        # one deposit flips four slopes: two 1 -> 0, two 0 -> 1
+        s = f.copy()
+        assert orc.attempt(s, 2, 0, True, False) == 1
+        assert orc.slope_overlap(s, f) == L * L - 2
+        assert orc.c_s(s, f) == 0.25 - 1.0 / (L * L)
