@@ -126,6 +126,66 @@ def batched_comparison(okpz, n_batched=200, n_plain=4, tune_mcs=10):
             "tuner_ms": {"%d/%.2f/%s" % k: v for k, v in tuned["times_ms"].items()}}
 
 
+def _serve_window(okpz, reqs, time_scale=1.0, chunk_mcs=64):
+    """Replay the requests' arrival times (scaled) against a fresh server and
+    return per-request latencies and the throughput of the window."""
+    srv = okpz.Server(chunk_mcs=chunk_mcs)
+    t0 = time.perf_counter()
+    for r in reqs:
+        wait = r.arrival * time_scale - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        srv.submit(r.L, r.Dx, r.Dy, r.Cx, r.Cy, r.scheme, 1, r.rid, r.n_mcs, r.p, r.q)
+    srv.drain(1200.0)
+    res = srv.poll(len(reqs) + 8)
+    st = srv.stats()
+    srv.close()
+    assert len(res) == len(reqs) and all(x["status"] == 0 for x in res)
+    lat = sorted(x["t_finish"] - x["t_submit"] for x in res)
+    span = max(x["t_finish"] for x in res) - min(x["t_submit"] for x in res)
+    attempts = sum(r.L * r.L * r.n_mcs for r in reqs)
+    import numpy as np
+
+    return {"requests": len(reqs), "attempts_per_s": attempts / span, "span_s": span,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "ticks": st["ticks"], "max_members": st["max_members"],
+            "offered_req_per_s": 1.0 / (time_scale * (reqs[-1].arrival / len(reqs)))}
+
+
+def served_comparison(okpz, n_requests=24, plain_mcs=20):
+    """The serving workload (Poisson arrivals at 200/s, L = 2^U{9..13}, 10^3 or
+    10^4 MCS, p ~ U[0.5,1], q = 1-p, DTrDB, D = min(256, L/2), TC=1,1): a
+    bounded window of the first requests replayed in real time (overloaded by
+    construction), then the same requests at about 70 % of the measured
+    capacity; against the plain path (each request alone, one lattice per
+    launch), timed on plain_mcs MCS of every request."""
+    from workloads import serving_requests
+
+    reqs = serving_requests(2000, 200.0, 1)[:n_requests]
+    over = _serve_window(okpz, reqs)
+    per_req = sum(r.L * r.L * r.n_mcs for r in reqs) / len(reqs)
+    capacity = over["attempts_per_s"] / per_req  # requests/s
+    target = 0.7 * capacity
+    scale = (reqs[-1].arrival / len(reqs)) * target
+    at70 = _serve_window(okpz, reqs, time_scale=1.0 / scale)
+    t_plain, a_plain = 0.0, 0
+    for r in reqs:
+        with okpz.Lattice(r.L, r.Dx, r.Dy, r.Cx, r.Cy, r.scheme, seed=1, stream=r.rid) as lat:
+            lat.run(1, r.p, r.q)
+            lat.sync()
+            t0 = time.perf_counter()
+            lat.run(plain_mcs, r.p, r.q)
+            lat.sync()
+            t_plain += time.perf_counter() - t0
+            a_plain += r.L * r.L * plain_mcs
+    plain = a_plain / t_plain
+    return {"workload": "serving: first %d requests of a Poisson stream at 200/s, L=2^U{9..13}, "
+                        "MCS in {1e3,1e4}, p~U[0.5,1], q=1-p, DTrDB, D=min(256,L/2), TC=1,1" % n_requests,
+            "overload": over, "at_70pct_capacity": at70, "capacity_req_per_s": capacity,
+            "plain_attempts_per_s": plain, "plain_mcs_per_request": plain_mcs,
+            "served_over_plain": over["attempts_per_s"] / plain}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving window")
+    ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -225,6 +287,9 @@ def main():
     if not args.no_batched:
         print("bench: batched vs plain", file=sys.stderr, flush=True)
         line["batched"] = batched_comparison(okpz)
+    if not args.no_served:
+        print("bench: serving window", file=sys.stderr, flush=True)
+        line["served"] = served_comparison(okpz, args.serve_requests)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (about %.0f s)" % args.cpu_budget, file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(L, D, C, scheme, p, q, args.cpu_budget)

@@ -119,15 +119,23 @@ typedef struct okpz_moments {
 } okpz_moments;
 
 /*
- * Height autocorrelation between the current state (time t) and the
- * snapshot (time s): C_h(t,s) = <h_t h_s> - <h_t><h_s> over sites (Sec. 2.1;
- * C_h(s,s) = W^2(s)).  s_ts = sum h_t h_s, s1_t = sum h_t, s1_s = sum h_s;
- * c_h = (N s_ts - s1_t s1_s) / N^2 rounded once to nearest.
+ * Autocorrelations between the current state (time t) and the snapshot
+ * (time s), Sec. 2.1:
+ *   heights: C_h(t,s) = <h_t h_s> - <h_t><h_s> over sites (C_h(s,s) = W^2(s)).
+ *     s_ts = sum h_t h_s, s1_t = sum h_t, s1_s = sum h_s;
+ *     c_h = (N s_ts - s1_t s1_s) / N^2 rounded once to nearest.
+ *   slopes (the lattice gas): C_s(t,s) = <n_t n_s> - <n_t><n_s> over the
+ *     2 L^2 slope variables (sx and sy of every site), where particle
+ *     conservation fixes <n> = 1/2 in every state.  overlap = number of slope
+ *     variables equal to 1 in both states; c_s = overlap / (2 L^2) - 1/4
+ *     (exact).
  */
 typedef struct okpz_correlation {
     uint64_t t, s;
     okpz_i128 s_ts, s1_t, s1_s;
     double c_h;
+    int64_t overlap;
+    double c_s;
 } okpz_correlation;
 
 typedef struct okpz_lattice okpz_lattice;
@@ -343,6 +351,74 @@ int okpz_batch_sync(okpz_batch *batch);
  * returns total milliseconds, launches and update attempts since enabled. */
 int okpz_batch_timing(okpz_batch *batch, int enable);
 int okpz_batch_get_timing(okpz_batch *batch, double *ms, uint64_t *launches, uint64_t *attempts);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  Requests (lattice
+ * parameters, MCS count, rates) are queued from any thread; a native worker
+ * thread admits them in arrival order while their device footprint fits the
+ * HBM budget and a member slot is free (flat initial lattice, resident on
+ * the GPU until the request retires), advances every admitted request by up
+ * to chunk_mcs MCS per tick in one persistent batch launch, and retires
+ * finished requests: final moments (as okpz_measure), optionally the final
+ * sites, timestamps.  Requests arriving while others run join at the next
+ * tick.  Each result equals running the request alone (okpz_create +
+ * okpz_run) bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct okpz_server okpz_server;
+
+typedef struct okpz_server_config {
+    uint64_t hbm_budget;  /* device bytes admitted requests may hold (> 0)          */
+    uint32_t max_members; /* requests on the GPU at once (> 0)                      */
+    uint32_t chunk_mcs;   /* MCS per request per tick (> 0)                         */
+    uint32_t threads;     /* batch launch shape, see okpz_batch_config (0 = default) */
+    uint32_t grid;
+    int32_t use_graph;    /* capture/replay ticks (ignored on the null stream)     */
+    uint32_t reserved;    /* 0 */
+} okpz_server_config;
+
+/* Result of one request.  Times are seconds on the server's steady clock
+ * (0 at okpz_server_create): submitted, admitted to the GPU, finished. */
+typedef struct okpz_result {
+    uint64_t id;
+    int32_t status; /* OKPZ_OK or the error that ended the request */
+    uint32_t L;
+    uint64_t n_mcs;
+    okpz_moments moments; /* at the end of the run */
+    double t_submit, t_start, t_finish;
+} okpz_result;
+
+typedef struct okpz_server_stats {
+    uint64_t submitted, finished, queued, admitted;
+    uint64_t ticks;       /* batch launches                               */
+    uint64_t attempts;    /* update attempts done                         */
+    uint64_t max_members; /* most requests on the GPU at once             */
+    double busy_seconds;  /* wall time inside ticks (launch to sync)      */
+    double clock;         /* server clock now                             */
+} okpz_server_stats;
+
+/* Start a server whose GPU work runs on hip_stream (NULL: null stream) of
+ * the calling thread's current device. */
+int okpz_server_create(const okpz_server_config *cfg, void *hip_stream, okpz_server **out);
+
+/* Queue a request (validated as okpz_create / okpz_run; ENOMEM if it can
+ * never fit the budget).  sites_out: NULL or an L*L host buffer (layout of
+ * okpz_get_sites) that receives the final state and must stay valid until
+ * the result has been polled.  *id numbers requests from 0. */
+int okpz_server_submit(okpz_server *srv, const okpz_params *params, uint64_t n_mcs, double p, double q,
+                       uint8_t *sites_out, uint64_t *id);
+
+/* Move up to max finished results into out (completion order); *n = count.
+ * Never blocks. */
+int okpz_server_poll(okpz_server *srv, okpz_result *out, uint32_t max, uint32_t *n);
+
+/* Block until every submitted request has finished (OKPZ_ESTATE on
+ * timeout); returns the first error the worker met, else OKPZ_OK. */
+int okpz_server_drain(okpz_server *srv, double timeout_seconds);
+
+int okpz_server_get_stats(okpz_server *srv, okpz_server_stats *out);
+
+/* Drop queued requests, finish the admitted ones, stop the worker, free. */
+int okpz_server_destroy(okpz_server *srv);
 
 #ifdef __cplusplus
 }

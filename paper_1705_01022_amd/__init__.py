@@ -80,6 +80,47 @@ class Correlation(ctypes.Structure):
         ("s1_t", I128),
         ("s1_s", I128),
         ("c_h", ctypes.c_double),
+        ("overlap", ctypes.c_int64),
+        ("c_s", ctypes.c_double),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_uint64),
+        ("max_members", ctypes.c_uint32),
+        ("chunk_mcs", ctypes.c_uint32),
+        ("threads", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+        ("use_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("L", ctypes.c_uint32),
+        ("n_mcs", ctypes.c_uint64),
+        ("moments", Moments),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_finish", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("finished", ctypes.c_uint64),
+        ("queued", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("ticks", ctypes.c_uint64),
+        ("attempts", ctypes.c_uint64),
+        ("max_members", ctypes.c_uint64),
+        ("busy_seconds", ctypes.c_double),
+        ("clock", ctypes.c_double),
     ]
 
 
@@ -131,6 +172,14 @@ _SIGS = {
     "okpz_batch_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_uint64),
                                               ctypes.POINTER(ctypes.c_uint64)]),
+    "okpz_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), _P, ctypes.POINTER(_P)]),
+    "okpz_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Params), ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_double, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "okpz_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(Result), ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32)]),
+    "okpz_server_drain": (ctypes.c_int, [_P, ctypes.c_double]),
+    "okpz_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
+    "okpz_server_destroy": (ctypes.c_int, [_P]),
 }
 
 _lib = None
@@ -279,7 +328,8 @@ class Lattice:
         ac = None
         if with_autocorr:
             ac = {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
-                  "s1_s": _to_int(c.s1_s), "c_h": c.c_h}
+                  "s1_s": _to_int(c.s1_s), "c_h": c.c_h,
+                  "overlap": c.overlap, "c_s": c.c_s}
         return mo, ac
 
     def snapshot(self):
@@ -289,7 +339,8 @@ class Lattice:
         c = Correlation()
         _check(load().okpz_autocorr(self._h, ctypes.byref(c)), "okpz_autocorr")
         return {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
-                "s1_s": _to_int(c.s1_s), "c_h": c.c_h}
+                "s1_s": _to_int(c.s1_s), "c_h": c.c_h,
+                  "overlap": c.overlap, "c_s": c.c_s}
 
     # -- export / import
     def sites(self) -> np.ndarray:
@@ -451,6 +502,88 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             load().okpz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _moments_dict(m: Moments) -> dict:
+    return {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
+            "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
+            "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
+            "w2": m.w2, "w2_sub": m.w2_sub}
+
+
+class Server:
+    """Request loop with continuous batching (native worker thread).
+
+    ``submit`` queues a simulation request and returns its id; ``poll``
+    returns finished results (dicts with the final moments, the final sites
+    if asked for, and submit/start/finish times on the server clock).
+    """
+
+    def __init__(self, hbm_budget=64 << 30, max_members=1024, chunk_mcs=64, threads=0, grid=0,
+                 use_graph=True, hip_stream=None):
+        lib = load()
+        self._torch_stream = None
+        if hip_stream is None:
+            import torch
+
+            self._torch_stream = torch.cuda.Stream()
+            hip_stream = self._torch_stream.cuda_stream
+        cfg = ServerConfig(hbm_budget, max_members, chunk_mcs, threads, grid, int(use_graph), 0)
+        h = ctypes.c_void_p()
+        _check(lib.okpz_server_create(ctypes.byref(cfg), ctypes.c_void_p(hip_stream), ctypes.byref(h)),
+               "okpz_server_create")
+        self._h = h
+        self._sites = {}  # id -> host buffer the worker writes the final sites into
+
+    def submit(self, L, Dx, Dy, Cx, Cy, scheme, seed, stream, n_mcs, p, q, want_sites=False) -> int:
+        prm = params(L, Dx, Dy, Cx, Cy, scheme, seed, stream)
+        buf = np.zeros((L, L), dtype=np.uint8) if want_sites else None
+        rid = ctypes.c_uint64()
+        _check(load().okpz_server_submit(self._h, ctypes.byref(prm), n_mcs, p, q,
+                                         _ptr(buf) if buf is not None else None, ctypes.byref(rid)),
+               "okpz_server_submit")
+        if buf is not None:
+            self._sites[rid.value] = buf
+        return rid.value
+
+    def poll(self, max_results=256) -> list:
+        arr = (Result * max_results)()
+        n = ctypes.c_uint32()
+        _check(load().okpz_server_poll(self._h, arr, max_results, ctypes.byref(n)), "okpz_server_poll")
+        out = []
+        for r in arr[:n.value]:
+            d = {"id": r.id, "status": r.status, "L": r.L, "n_mcs": r.n_mcs,
+                 "moments": _moments_dict(r.moments), "t_submit": r.t_submit, "t_start": r.t_start,
+                 "t_finish": r.t_finish}
+            if r.id in self._sites:
+                d["sites"] = self._sites.pop(r.id)
+            out.append(d)
+        return out
+
+    def drain(self, timeout=600.0):
+        _check(load().okpz_server_drain(self._h, timeout), "okpz_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().okpz_server_get_stats(self._h, ctypes.byref(st)), "okpz_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().okpz_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

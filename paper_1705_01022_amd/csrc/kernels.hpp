@@ -513,7 +513,7 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
     return v;
 }
 
-constexpr int kMomentFields = 5;  // S1_even, S1_odd, S2_even, S2_odd, S_ts
+constexpr int kMomentFields = 6;  // S1_even, S1_odd, S2_even, S2_odd, S_ts, slope overlap
 
 // Row-nibble table: for 4 consecutive sites of a row (x % 4 = 0..3) with
 // steps e_i = 2 b_i - 1 (e_0 = 0 for the row's first site, entries 16..31)
@@ -557,7 +557,9 @@ constexpr int kMeasureThreads = 256;
 // block's start, a wave scan gives the block offsets, and the relative sums
 // are shifted to absolute heights: with A the height before the block and q
 // the relative heights, sum h = n A + sum q and sum h^2 = n A^2 + 2 A sum q +
-// sum q^2.  With a snapshot (CROSS), sum h_t h_s is accumulated the same way.
+// sum q^2.  With a snapshot (CROSS), sum h_t h_s is accumulated the same way,
+// and the slope overlap (slope variables that are 1 in both states, for the
+// slope autocorrelation C_s) is a population count of the ANDed words.
 template <bool CROSS>
 __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *__restrict__ words,
                                                                const int32_t *__restrict__ h0,
@@ -576,13 +578,20 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
     const uint64_t band_base = (static_cast<uint64_t>(band) << nbx_log2) << 3;
     int32_t carry[4] = {0, 0, 0, 0}, carry_s[4] = {0, 0, 0, 0};
     int64_t s1e = 0, s1o = 0, s2e = 0, s2o = 0, sts = 0;
+    uint32_t overlap = 0;  // at most 8 L per band
     for (uint32_t base = 0; base < nbx; base += 64) {
         const uint32_t bx = base + lane;
         const bool active = bx < nbx;
         uint4 wv = make_uint4(0, 0, 0, 0), sv = make_uint4(0, 0, 0, 0);
         if (active) {
             wv = *reinterpret_cast<const uint4 *>(words + band_base + 8u * bx);  // sx rows 0..3
-            if (CROSS) sv = *reinterpret_cast<const uint4 *>(snap + band_base + 8u * bx);
+            if (CROSS) {
+                sv = *reinterpret_cast<const uint4 *>(snap + band_base + 8u * bx);
+                const uint4 wy = *reinterpret_cast<const uint4 *>(words + band_base + 8u * bx + 4u);  // sy rows
+                const uint4 sy = *reinterpret_cast<const uint4 *>(snap + band_base + 8u * bx + 4u);
+                overlap += __popc(wv.x & sv.x) + __popc(wv.y & sv.y) + __popc(wv.z & sv.z) + __popc(wv.w & sv.w) +
+                           __popc(wy.x & sy.x) + __popc(wy.y & sy.y) + __popc(wy.z & sy.z) + __popc(wy.w & sy.w);
+            }
         }
         const uint32_t wk[4] = {wv.x, wv.y, wv.z, wv.w};
         const uint32_t sk[4] = {sv.x, sv.y, sv.z, sv.w};
@@ -642,7 +651,11 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
     s1o = wave_sum_i64(s1o);
     s2e = wave_sum_i64(s2e);
     s2o = wave_sum_i64(s2o);
-    if (CROSS) sts = wave_sum_i64(sts);
+    int64_t ov = 0;
+    if (CROSS) {
+        sts = wave_sum_i64(sts);
+        ov = wave_sum_i64((int64_t)overlap);
+    }
     if (lane == 0) {
         int64_t *out = partial + static_cast<uint64_t>(band) * kMomentFields;
         out[0] = s1e;
@@ -650,6 +663,7 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
         out[2] = s2e;
         out[3] = s2o;
         out[4] = sts;
+        out[5] = ov;
     }
 }
 

@@ -475,6 +475,10 @@ void fill_correlation(const okpz_lattice *lat, okpz_correlation *out)
     out->s1_t = to_abi(s1t);
     out->s1_s = to_abi(lat->snap_s1);
     out->c_h = std::ldexp(i128_to_double(n * sts - s1t * lat->snap_s1), -4 * (int)ilog2(L));
+    // C_s = overlap / (2 L^2) - 1/4 = (2 overlap - L^2) / (4 L^2)
+    const __int128 ov = pair_to_i128(lat->host_out + 10);
+    out->overlap = (int64_t)ov;
+    out->c_s = std::ldexp(i128_to_double(2 * ov - n), -2 - 2 * (int)ilog2(L));
 }
 
 }  // namespace

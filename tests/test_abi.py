@@ -50,6 +50,9 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(okpz_moments, s1_even), offsetof(okpz_moments, w2),
          offsetof(okpz_moments, w2_sub));
   printf("%zu %zu\n", offsetof(okpz_correlation, s_ts), offsetof(okpz_correlation, c_h));
+  printf("%zu %zu %zu\n", sizeof(okpz_server_config), sizeof(okpz_result), sizeof(okpz_server_stats));
+  printf("%zu %zu %zu %zu\n", offsetof(okpz_server_config, use_graph), offsetof(okpz_result, moments),
+         offsetof(okpz_result, t_finish), offsetof(okpz_server_stats, clock));
   return 0;
 }
 """
@@ -69,6 +72,12 @@ def test_struct_layouts_match_c(okpz, tmp_path):
     assert offs == [okpz.Moments.s1_even.offset, okpz.Moments.w2.offset, okpz.Moments.w2_sub.offset]
     offs = [int(v) for v in lines[2].split()]
     assert offs == [okpz.Correlation.s_ts.offset, okpz.Correlation.c_h.offset]
+    sizes = [int(v) for v in lines[3].split()]
+    assert sizes == [ctypes.sizeof(okpz.ServerConfig), ctypes.sizeof(okpz.Result),
+                     ctypes.sizeof(okpz.ServerStats)]
+    offs = [int(v) for v in lines[4].split()]
+    assert offs == [okpz.ServerConfig.use_graph.offset, okpz.Result.moments.offset,
+                    okpz.Result.t_finish.offset, okpz.ServerStats.clock.offset]
 
 
 @pytest.mark.parametrize("prm,ok", [

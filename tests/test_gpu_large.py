@@ -6,8 +6,8 @@ DTrDB, p=0.95, q=0.05).
   boundary) equals the oracle's window emulation on every site the oracle can
   determine (domains wholly inside the window);
 * moments: flat state and a flat state with a local bump written in, against
-  closed forms (flat moments analytic; the bump's contribution from the
-  oracle's heights of the bumped piece);
+  closed forms (flat moments analytic; the bump's contribution to the height
+  moments, C_h and C_s from the oracle's values on the bumped piece);
 * invariants: particle conservation per sampled row and column, plaquette
   closure on sampled windows, C_h(s,s) = W^2(s), after several MCS.
 """
@@ -88,6 +88,11 @@ def test_local_bump_moments_and_autocorr(big, orc):
     s1_s = n // 2
     assert ac["s_ts"] == s_ts and ac["s1_t"] == s1_t and ac["s1_s"] == s1_s
     assert ac["c_h"] == float(Fraction(n * s_ts - s1_t * s1_s, n * n))
+    # C_s: the flat lattice overlaps itself in L^2 slope variables; inside the
+    # bumped piece the overlap is the piece's own overlap with flat
+    ov = n - orc.slope_overlap(flat_piece, flat_piece) + orc.slope_overlap(piece, flat_piece)
+    assert ac["overlap"] == ov
+    assert ac["c_s"] == float(Fraction(ov, 2 * n) - Fraction(1, 4))
 
 
 def test_one_mcs_window_parity(big, orc):
@@ -115,6 +120,7 @@ def test_invariants_after_several_mcs(big):
     mo = big.measure()
     ac = big.autocorr()
     assert ac["c_h"] == mo["w2"] and ac["s_ts"] == mo["s2_even"] + mo["s2_odd"]
+    assert ac["c_s"] == 0.25 and ac["overlap"] == L * L
     assert mo["w2"] > 0.25
     rng = np.random.default_rng(3)
     for y in rng.integers(0, L, 3):

@@ -151,6 +151,8 @@ def test_l4096_full_compare(okpz, orc, scheme, pq):
         ac = lat.autocorr()
         assert ac["c_h"] == orc.c_h(ref, s_ref)
         assert ac["s_ts"] == orc.cross(ref, s_ref)
+        assert ac["overlap"] == orc.slope_overlap(ref, s_ref)
+        assert ac["c_s"] == orc.c_s(ref, s_ref)
 
 
 def test_autocorr_and_snapshot(okpz, orc):
@@ -167,6 +169,7 @@ def test_autocorr_and_snapshot(okpz, orc):
         ac = lat.autocorr()
         mo = lat.measure()
         assert ac["c_h"] == mo["w2"]  # C_h(s,s) = W^2(s)
+        assert ac["c_s"] == 0.25 and ac["overlap"] == 64 * 64  # C_s(s,s) = 1/4
         for m in range(5, 40):
             lat.run(1, 0.95, 0.05)
             e.mcs(ref, m)
@@ -174,6 +177,8 @@ def test_autocorr_and_snapshot(okpz, orc):
             assert ac["t"] == m + 1 and ac["s"] == 5
             assert ac["s_ts"] == orc.cross(ref, snap)
             assert ac["c_h"] == orc.c_h(ref, snap)
+            assert ac["overlap"] == orc.slope_overlap(ref, snap)
+            assert ac["c_s"] == orc.c_s(ref, snap)
 
 
 def test_observe_matches_measure_and_autocorr(okpz, orc):
@@ -197,6 +202,7 @@ def test_observe_matches_measure_and_autocorr(okpz, orc):
             assert mo == lat.measure()
             assert ac == lat.autocorr()
             assert ac["c_h"] == orc.c_h(ref, snap)
+            assert ac["c_s"] == orc.c_s(ref, snap)
 
 
 @pytest.mark.parametrize("scheme,pq,shape", [(0, (1.0, 0.0), (256, 64, 64, 4, 4)),
