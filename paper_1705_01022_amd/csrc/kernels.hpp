@@ -78,9 +78,6 @@ struct StepArgs {
     uint32_t P_hi, P_lo, Q_hi, Q_lo;  // acceptance thresholds on the (A+32)-bit variate
 };
 
-// Slope pattern of an attempt: bit 0 sx(x,y), bit 1 sx(x+1,y), bit 2 sy(x,y),
-// bit 3 sy(x,y+1).  Local minimum (0,1,0,1) = 0xA, local maximum = 0x5.
-constexpr uint32_t kPatternMin = 0xAu, kPatternMax = 0x5u;
 
 // LDS staging.  The window covers bands by0 .. by0+NB-1 and blocks
 // bx0 .. bx0+NWX-1 (periodic) of the lattice, i.e. the domain plus the column
@@ -121,13 +118,17 @@ __device__ __forceinline__ void copy_window(const StepArgs &A, uint32_t *lds, ui
     }
 }
 
+// Slope pattern of an attempt: bit 0 sx(x,y), bit 1 sx(x+1,y), bit 2 sy(x,y),
+// bit 3 sy(x,y+1).  Local minimum (0,1,0,1) = 0xA, local maximum = 0x5.
+constexpr uint32_t kPatternMin = 0xAu, kPatternMax = 0x5u;
+
 // One cell's attempt in one round, decoded from its lane draw.
 struct Draw {
     uint32_t ix;    // byte offset of the site's sx-plane word: 4 (row * P + column / 32)
     uint32_t iy;    // byte offset of its sy-plane word: 4 (sy_base + (column / 32) * PY + row)
     uint32_t sh;    // site bit in those words (column % 32)
-    uint32_t upre;  // acceptance prefix (top F - s_bits bits of the field)
-    uint32_t rlo;   // low 32 bits of the acceptance variate (drawn only on a prefix tie)
+    uint32_t mask;  // flip mask: bit kPatternMin set iff a local minimum here
+                    // deposits, bit kPatternMax iff a local maximum is removed
     uint32_t pos;   // domain-local u | v << 16
     uint32_t rim;   // bit 0: right column of its cell, bit 1: bottom row (DB)
 };
@@ -208,35 +209,100 @@ __device__ __forceinline__ Draw decode(const StepArgs &A, uint32_t field, uint32
     d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
     d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
     d.sh = lx & 31u;
-    d.upre = ACCEPT ? field >> A.s_bits : 0u;
-    d.rlo = 0u;
+    d.mask = ACCEPT ? field >> A.s_bits : A.flip_table;  // acceptance prefix until accept_draws()
     d.pos = SCHEME == kDB ? u | (v << 16) : 0u;
     d.rim = SCHEME == kDB ? ((du == (1u << A.log2Cx) - 1u) ? 1u : 0u) | ((dv == (1u << A.log2Cy) - 1u) ? 2u : 0u)
                           : 0u;
     return d;
 }
 
-// Low word of the acceptance variate, needed only when the prefix equals the
-// prefix of P or Q (probability about 2^(1-A)): word 0 of Philox block
-// (rho, cell | 0x80000000, tile, 4*MCS+step).
+// DB: what a cell keeps of its drawn attempt between the draw (one round
+// ahead) and the attempt: the domain-local site, the flip mask (bits
+// kPatternMin and kPatternMax) and the rim bits; the LDS addresses are derived
+// again when the attempt runs.
+struct CDraw {
+    uint32_t pos;  // u | v << 16
+    uint32_t ur;   // flip mask | rim (bit 0 right column, bit 1 bottom row); before
+                   // accept_draws(): acceptance prefix << 2 | rim
+};
+
 template <bool ACCEPT>
-__device__ __forceinline__ void draw_tie(const StepArgs &A, Draw &d, uint32_t rho, uint32_t cell, uint32_t tile)
+__device__ __forceinline__ CDraw decode_db(const StepArgs &A, uint32_t field, uint32_t f16, uint32_t base_u,
+                                           uint32_t base_v)
 {
-    if (ACCEPT && (d.upre == A.P_hi || d.upre == A.Q_hi))
-        d.rlo = philox4x32_10(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
+    const uint32_t idx = field & ((1u << A.s_bits) - 1u);
+    const uint32_t cxm = (1u << A.log2Cx) - 1u, cym = (1u << A.log2Cy) - 1u;
+    const uint32_t du = idx & cxm, dv = idx >> A.log2Cx;
+    const uint32_t shx = (f16 >> 2) & cxm, shy = (f16 >> 8) & cym;
+    const uint32_t u = (shx + base_u + du) & (A.Dx - 1u);
+    const uint32_t v = (shy + base_v + dv) & (A.Dy - 1u);
+    CDraw c;
+    c.pos = u | (v << 16);
+    c.ur = (ACCEPT ? (field >> A.s_bits) << 2 : 0u) | (du == cxm ? 1u : 0u) | (dv == cym ? 2u : 0u);
+    return c;
+}
+
+// Acceptance (Sec. 2.1 rates) of every cell's attempt of round rho, turned
+// into flip masks.  The acceptance variate is U = prefix * 2^32 + r: a
+// deposition is accepted iff U < P, a removal iff U < Q.  The prefix decides
+// unless it equals the top bits of P or Q (probability about 2^(1-A)); only
+// then r, word 0 of Philox block (rho, cell | 0x80000000, tile, 4*MCS+step),
+// is drawn -- by a branch the whole wave skips when no lane needs it.
+// pre[j]: the prefixes in, the masks out.
+template <int CPT>
+__device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[CPT], uint32_t rho, uint32_t tile)
+{
+    bool tie[CPT];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        tie[j] = pre[j] == A.P_hi || pre[j] == A.Q_hi;
+        any |= tie[j];
+    }
+    uint32_t mask[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+        mask[j] = (pre[j] < A.P_hi ? 1u << kPatternMin : 0u) | (pre[j] < A.Q_hi ? 1u << kPatternMax : 0u);
+    if (__ballot(any)) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (tie[j]) {
+                const uint32_t r =
+                    philox4x32_10(A.key0, A.key1, rho, (threadIdx.x * CPT + j) | 0x80000000u, tile, A.c3).x;
+                if (pre[j] == A.P_hi && r < A.P_lo) mask[j] |= 1u << kPatternMin;
+                if (pre[j] == A.Q_hi && r < A.Q_lo) mask[j] |= 1u << kPatternMax;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) pre[j] = mask[j];
+}
+
+// The full attempt of a DB cell from its compact draw.
+template <bool ACCEPT>
+__device__ __forceinline__ Draw expand(const StepArgs &A, const CDraw &c, uint32_t offx, uint32_t offy)
+{
+    const uint32_t lx = (c.pos & 0xFFFFu) + offx, ly = (c.pos >> 16) + offy;
+    Draw d;
+    d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
+    d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
+    d.sh = lx & 31u;
+    d.mask = ACCEPT ? c.ur & ~3u : A.flip_table;
+    d.pos = c.pos;
+    d.rim = c.ur & 3u;
+    return d;
 }
 
 // One update attempt (Sec. 2.1 rule) at the site of d.  With the window as
 // bit planes, a = sx(x,y) and b = sx(x+1,y) are two adjacent bits of the sx
 // row (a funnel shift over the word and the next one), c = sy(x,y) and
 // d = sy(x,y+1) the same bit of two consecutive sy rows.  A local minimum
-// (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed; both flip
-// the same four bits with LDS atomic XORs (zero masks when nothing flips, or
-// when `enable` is false), because attempts of different cells may share a
-// word (never a bit).  All decisions are bitwise; the only branch guards the
-// rare flip of sx(x+1) in the next word (x at bit 31).
-template <bool ACCEPT>
-__device__ __forceinline__ void attempt(const StepArgs &A, uint32_t *lds, const Draw &d, bool enable = true)
+// (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed (as the
+// draw's flip mask says); both flip the same four bits with LDS atomic XORs
+// (zero masks when nothing flips, or when `enable` is false), because attempts
+// of different cells may share a word (never a bit).  All decisions are
+// bitwise; the only branch guards the rare flip of sx(x+1) in the next word (x
+// at bit 31).
+__device__ __forceinline__ void attempt(uint32_t *lds, const Draw &d, bool enable = true)
 {
     char *base = reinterpret_cast<char *>(lds);
     uint32_t *px = reinterpret_cast<uint32_t *>(base + d.ix);
@@ -245,19 +311,8 @@ __device__ __forceinline__ void attempt(const StepArgs &A, uint32_t *lds, const 
     const uint32_t y0 = py[0], y1 = py[1];
     const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, d.sh) & 3u;
     const uint32_t key = ab | (__builtin_amdgcn_ubfe(y0, d.sh, 1) << 2) | (__builtin_amdgcn_ubfe(y1, d.sh, 1) << 3);
-    uint32_t flip;
-    if (ACCEPT) {
-        // U = (upre << 32) | rlo below P (deposition) or Q (removal)
-        const bool is_min = key == kPatternMin;
-        const uint32_t thr_hi = is_min ? A.P_hi : A.Q_hi;
-        const uint32_t thr_lo = is_min ? A.P_lo : A.Q_lo;
-        const uint32_t below = (d.upre < thr_hi ? 1u : 0u) | ((d.upre == thr_hi ? 1u : 0u) & (d.rlo < thr_lo ? 1u : 0u));
-        flip = (((1u << kPatternMin) | (1u << kPatternMax)) >> key) & below;
-    } else {
-        flip = A.flip_table >> key;
-    }
-    flip &= enable ? 1u : 0u;
-    const uint32_t m = (flip & 1u) << d.sh;
+    const uint32_t flip = __builtin_amdgcn_ubfe(d.mask, key, 1) & (enable ? 1u : 0u);
+    const uint32_t m = flip << d.sh;
     atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
     atomicXor(&py[0], m);             // sy(x, y)
     atomicXor(&py[1], m);             // sy(x, y+1)
@@ -273,61 +328,121 @@ struct CellGeom {
     uint32_t nb;    // published-site slots of the cells to the right (low 16 bits) and below
 };
 
+// Orders the LDS accesses of one wave: everything before completes, in
+// program order, before anything after (a wave's LDS instructions execute in
+// issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // DB: draw round rho+1 for every cell of the thread into nxt and publish
-// the sites (buffer (rho+1) & 1), then run round rho whose draws are in cur:
-// the attempts that do not depend on phase order at once, the deferred ones
-// after the barrier in phase order.
+// the sites (buffer (rho+1) & 1), then run round rho whose draws are in cur.
+//
+// Delayed borders apply a round's attempts as bulk (phase 0), then edges
+// (phase 1: right column or bottom row of the cell), then the corner
+// (phase 2).  Only a rim attempt whose right or lower neighbour site holds the
+// neighbouring cell's attempt depends on that order ("deferred"); all other
+// attempts run in the first pass.  Dependencies point right (same cell row)
+// or down (next cell row).  With `inwave`, every wave holds whole cell rows,
+// at least two of them (or all of them), so the only deferred attempts with a
+// dependency in another wave are bottom-row and corner attempts in a wave's
+// last cell row ("remote"); their dependents are remote too.  Every other
+// deferred attempt runs in its own wave right after the first pass, edges
+// before corners, without a workgroup barrier; remote ones run after the
+// round's barrier (edges, then corners, in program order), followed by one
+// more barrier.  Without `inwave`, all deferred edges, then all deferred
+// corners, run after barriers.
 template <bool ACCEPT, int CPT>
 __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint32_t *cpos, uint32_t *flags,
                                          const CellGeom (&g)[CPT], uint32_t (&rw)[CPT][4], BlockDraw &bd,
-                                         Draw (&cur)[CPT], Draw (&nxt)[CPT], uint32_t rho, uint32_t tile,
-                                         uint32_t offx, uint32_t offy, const bool (&act)[CPT])
+                                         CDraw (&cur)[CPT], CDraw (&nxt)[CPT], uint32_t rho, uint32_t tile,
+                                         uint32_t offx, uint32_t offy, const bool (&act)[CPT],
+                                         const bool (&border)[CPT], bool inwave)
 {
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     if (rho + 1u < A.rounds) {
         const uint32_t f16 = next_block_field(A, bd, rho + 1u, tile);
         const uint32_t nbuf = ((rho + 1u) & 1u) * (NT * CPT);
+        uint32_t pre[CPT];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const uint32_t field = next_field(A, rw[j], rho + 1u, tid * CPT + j, tile);
-            nxt[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
+            nxt[j] = decode_db<ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16);
             if (act[j]) cpos[nbuf + j * NT + tid] = nxt[j].pos;
+            pre[j] = nxt[j].ur >> 2;
         }
+        if (ACCEPT) {
+            accept_draws<CPT>(A, pre, rho + 1u, tile);
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, nxt[j], rho + 1u, tid * CPT + j, tile);
+            for (int j = 0; j < CPT; ++j) nxt[j].ur = pre[j] | (nxt[j].ur & 3u);
+        }
     }
     // A rim attempt waits if the neighbouring cell's attempt sits on the site
     // to its right (right column / corner) or below it (bottom row / corner).
     // A target one past the domain edge is never a published site.
     const uint32_t buf = (rho & 1u) * (NT * CPT);
-    bool def[CPT];
+    bool def[CPT], remote[CPT];
     bool any1 = false, any2 = false;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const uint32_t pr = cpos[buf + (g[j].nb & 0xFFFFu)], pd = cpos[buf + (g[j].nb >> 16)];
-        const uint32_t want_r = (cur[j].rim & 1u) ? cur[j].pos + 1u : 0xFFFFFFFFu;
-        const uint32_t want_d = (cur[j].rim & 2u) ? cur[j].pos + 0x10000u : 0xFFFFFFFFu;
+        const uint32_t rim = cur[j].ur & 3u;
+        const uint32_t want_r = (rim & 1u) ? cur[j].pos + 1u : 0xFFFFFFFFu;
+        const uint32_t want_d = (rim & 2u) ? cur[j].pos + 0x10000u : 0xFFFFFFFFu;
         def[j] = act[j] && (pr == want_r || pd == want_d);
-        any1 |= def[j] && cur[j].rim != 3u;
-        any2 |= def[j] && cur[j].rim == 3u;
+        remote[j] = inwave ? def[j] && border[j] && (rim & 2u) : def[j];
+        any1 |= remote[j] && rim != 3u;
+        any2 |= remote[j] && rim == 3u;
     }
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, cur[j], !def[j] && act[j]);
+    for (int j = 0; j < CPT; ++j)
+        attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy), !def[j] && act[j]);
+    if (inwave) {
+        wave_order();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)  // local deferred edges
+            if (def[j] && !remote[j] && (cur[j].ur & 3u) != 3u)
+                attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
+        wave_order();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)  // local deferred corners
+            if (def[j] && !remote[j] && (cur[j].ur & 3u) == 3u)
+                attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
+    }
     const uint64_t b1 = __ballot(any1), b2 = __ballot(any2);
     if ((tid & 63u) == 0u && (b1 | b2)) atomicOr(&flags[rho % 3u], (b1 ? 1u : 0u) | (b2 ? 2u : 0u));
     if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
     __syncthreads();
     const uint32_t f = flags[rho % 3u];
+    if (inwave) {
+        if (f) {  // remote edges, then remote corners of the same waves
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                if (remote[j] && (cur[j].ur & 3u) != 3u)
+                    attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
+            wave_order();
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                if (remote[j] && (cur[j].ur & 3u) == 3u)
+                    attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
+            __syncthreads();
+        }
+        return;
+    }
     if (f & 1u) {  // deferred edge attempts
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
-            if (def[j] && cur[j].rim != 3u) attempt<ACCEPT>(A, lds, cur[j]);
+            if (def[j] && (cur[j].ur & 3u) != 3u)
+                attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
         __syncthreads();
     }
     if (f & 2u) {  // deferred corner attempts
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
-            if (def[j] && cur[j].rim == 3u) attempt<ACCEPT>(A, lds, cur[j]);
+            if (def[j] && (cur[j].ur & 3u) == 3u)
+                attempt(lds, expand<ACCEPT>(A, cur[j], offx, offy));
         __syncthreads();
     }
 }
@@ -385,7 +500,10 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
     auto slot_of = [&](uint32_t c) { return (c % CPT) * NT + c / CPT; };
     CellGeom g[CPT];
     uint32_t rw[CPT][4];
-    bool act[CPT];
+    bool act[CPT], border[CPT];
+    // DB: waves hold whole cell rows, at least two of them or all of them
+    const uint32_t cpw = 64u * CPT, ncx = 1u << A.log2ncx;
+    const bool inwave = A.ncell <= cpw || (ncx <= cpw / 2u);
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         // a thread's cells are horizontal neighbours, so the lanes of one
@@ -393,6 +511,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
         const uint32_t cell = tid * CPT + j;
         const uint32_t cx = cell & ncx_mask, cy = (cell >> A.log2ncx) & ncy_mask;
         act[j] = FULL || cell < A.ncell;
+        border[j] = ((cell + ncx) & (A.ncell - 1u)) / cpw != cell / cpw;  // the cell below is in another wave
         g[j].base = (cx << A.log2Cx) | ((cy << A.log2Cy) << 16);
         g[j].nb = slot_of((cy << A.log2ncx) | ((cx + 1u) & ncx_mask)) |
                   (slot_of((((cy + 1u) & ncy_mask) << A.log2ncx) | cx) << 16);
@@ -410,29 +529,41 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
                 const uint32_t field = next_field(A, rw[j], rho, tid * CPT + j, tile);
                 d[j] = decode<SCHEME, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
             }
+            if (ACCEPT) {
+                uint32_t pre[CPT];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, d[j], rho, tid * CPT + j, tile);
+                for (int j = 0; j < CPT; ++j) pre[j] = d[j].mask;
+                accept_draws<CPT>(A, pre, rho, tile);
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) attempt<ACCEPT>(A, lds, d[j], act[j]);
+                for (int j = 0; j < CPT; ++j) d[j].mask = pre[j];
+            }
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) attempt(lds, d[j], act[j]);
             __syncthreads();
         }
     } else {
-        Draw da[CPT], db[CPT];
+        CDraw da[CPT], db[CPT];
         const uint32_t f16 = next_block_field(A, bd, 0u, tile);
+        uint32_t pre[CPT];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const uint32_t field = next_field(A, rw[j], 0u, tid * CPT + j, tile);
-            da[j] = decode<kDB, ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16, offx, offy);
+            da[j] = decode_db<ACCEPT>(A, field, f16, g[j].base & 0xFFFFu, g[j].base >> 16);
             if (act[j]) cpos[j * NT + tid] = da[j].pos;
+            pre[j] = da[j].ur >> 2;
         }
+        if (ACCEPT) {
+            accept_draws<CPT>(A, pre, 0u, tile);
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) draw_tie<ACCEPT>(A, da[j], 0u, tid * CPT + j, tile);
+            for (int j = 0; j < CPT; ++j) da[j].ur = pre[j] | (da[j].ur & 3u);
+        }
         if (tid < 3) flags[tid] = 0u;
         __syncthreads();
         // Cx*Cy rounds, an even number: alternate the two draw buffers
         for (uint32_t rho = 0; rho < A.rounds; rho += 2) {
-            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, da, db, rho, tile, offx, offy, act);
-            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, db, da, rho + 1u, tile, offx, offy, act);
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, da, db, rho, tile, offx, offy, act, border, inwave);
+            db_round<ACCEPT, CPT>(A, lds, cpos, flags, g, rw, bd, db, da, rho + 1u, tile, offx, offy, act, border,
+                                  inwave);
         }
     }
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);

@@ -1,0 +1,94 @@
+"""Statistics of the GPU DTr dynamics against sequential RS and KPZ scaling.
+
+The decomposition changes the non-universal prefactor of the roughness
+(finer decompositions sample the lattice more evenly and roughen slightly
+less, Sec. 4.2) but not the growth exponent.  So:
+
+* at L = 128, the GPU DTrDB W^2(t) of 64 realisations and the oracle's
+  sequential RS W^2(t) of 64 realisations have the same effective growth
+  exponent (Eq. `eq:effexp`) within 3 standard errors, and differ by a few
+  percent at most at every time (the signed deviations are printed);
+* at L = 2048 (growth regime, t << L^z), the effective exponent over the
+  last decade of a 4096-MCS run is within max(3 sigma, 0.02) of the KPZ value
+  beta = 0.2414 (Sec. 2.1).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TIMES = [1, 2, 4, 8, 16, 32, 64, 128]
+
+
+def gpu_series(okpz, L, D, C, scheme, p, q, n, times, seed):
+    b = okpz.Batch()
+    lats = [b.lattice(L, D, D, C, C, scheme, seed=seed, stream=r) for r in range(n)]
+    out = np.zeros((n, len(times)))
+    t = 0
+    for i, tt in enumerate(times):
+        b.run([tt - t] * n, p, q)
+        b.sync()
+        t = tt
+        for r, lat in enumerate(lats):
+            out[r, i] = lat.measure()["w2"]
+    b.close()
+    for lat in lats:
+        lat.close()
+    return out
+
+
+def seq_series(orc, L, p, q, n, times, seed):
+    out = np.zeros((n, len(times)))
+    for r in range(n):
+        rs = orc.SeqRS(L, p, q, seed=seed, stream=r)
+        t = 0
+        for i, tt in enumerate(times):
+            rs.run(tt - t)
+            t = tt
+            out[r, i] = orc.w2(rs.s)
+    return out
+
+
+def beta_eff(w2, times, i, j):
+    """Effective exponent (Eq. `eq:effexp`) of W = sqrt(<W^2>) between
+    times[i] < times[j], with its standard error from the sample means (delta
+    method, covariance of the two means taken from the runs)."""
+    n = w2.shape[0]
+    mi, mj = w2[:, i].mean(), w2[:, j].mean()
+    span = math.log(times[j] / times[i])
+    b = 0.5 * math.log(mj / mi) / span
+    c = np.cov(w2[:, i], w2[:, j]) / n
+    g = np.array([-0.5 / mi, 0.5 / mj])
+    return b, math.sqrt(float(g @ c @ g)) / span
+
+
+def test_roughness_growth_matches_sequential_rs(okpz, orc):
+    L, D, C, p, q, n = 128, 32, 8, 1.0, 0.0, 64
+    g = gpu_series(okpz, L, D, C, okpz.BLOCK_DB, p, q, n, TIMES, seed=5)
+    s = seq_series(orc, L, p, q, n, TIMES, seed=11)
+    print("\nt  W2_seq  W2_DTrDB  rel.dev  z")
+    for i, t in enumerate(TIMES):
+        ms, mg = s[:, i].mean(), g[:, i].mean()
+        se = math.sqrt(s[:, i].var(ddof=1) / n + g[:, i].var(ddof=1) / n)
+        print("%4d %.4f %.4f %+.4f %+.2f" % (t, ms, mg, (mg - ms) / ms, (mg - ms) / se))
+        # the decomposition's prefactor effect: a few percent at most
+        assert abs(mg - ms) / ms < 0.05, t
+    # same growth exponent over the last decade-and-a-bit
+    bg, eg = beta_eff(g, TIMES, 3, 7)
+    bs, es = beta_eff(s, TIMES, 3, 7)
+    print("beta_eff(8..128): DTrDB %.4f +- %.4f, sequential %.4f +- %.4f" % (bg, eg, bs, es))
+    assert abs(bg - bs) < 3 * math.hypot(eg, es)
+
+
+def test_growth_exponent_is_kpz(okpz):
+    times = [64, 128, 256, 512, 1024, 2048, 4096]
+    L, D, C, n = 2048, 256, 8, 16
+    g = gpu_series(okpz, L, D, C, okpz.BLOCK_DB, 1.0, 0.0, n, times, seed=9)
+    for i in range(1, len(times)):
+        b, e = beta_eff(g, times, i - 1, i)
+        print("beta_eff(%d..%d) = %.4f +- %.4f" % (times[i - 1], times[i], b, e))
+    b, e = beta_eff(g, times, 3, 6)  # 512 .. 4096
+    print("beta_eff(512..4096) = %.4f +- %.4f" % (b, e))
+    assert abs(b - 0.2414) < max(3 * e, 0.02)
