@@ -248,9 +248,10 @@ __device__ __forceinline__ CDraw decode_db(const StepArgs &A, uint32_t field, ui
 // unless it equals the top bits of P or Q (probability about 2^(1-A)); only
 // then r, word 0 of Philox block (rho, cell | 0x80000000, tile, 4*MCS+step),
 // is drawn -- by a branch the whole wave skips when no lane needs it.
-// pre[j]: the prefixes in, the masks out.
+// pre[j]: the prefixes in, the masks out; cell[j]: the cells' ids.
 template <int CPT>
-__device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[CPT], uint32_t rho, uint32_t tile)
+__device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[CPT], const uint32_t (&cell)[CPT],
+                                             uint32_t rho, uint32_t tile)
 {
     bool tie[CPT];
     bool any = false;
@@ -267,8 +268,7 @@ __device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
             if (tie[j]) {
-                const uint32_t r =
-                    philox4x32_10(A.key0, A.key1, rho, (threadIdx.x * CPT + j) | 0x80000000u, tile, A.c3).x;
+                const uint32_t r = philox4x32_10(A.key0, A.key1, rho, cell[j] | 0x80000000u, tile, A.c3).x;
                 if (pre[j] == A.P_hi && r < A.P_lo) mask[j] |= 1u << kPatternMin;
                 if (pre[j] == A.Q_hi && r < A.Q_lo) mask[j] |= 1u << kPatternMax;
             }
@@ -374,7 +374,10 @@ __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint3
             pre[j] = nxt[j].ur >> 2;
         }
         if (ACCEPT) {
-            accept_draws<CPT>(A, pre, rho + 1u, tile);
+            uint32_t ids[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) ids[j] = tid * CPT + j;
+            accept_draws<CPT>(A, pre, ids, rho + 1u, tile);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) nxt[j].ur = pre[j] | (nxt[j].ur & 3u);
         }
@@ -533,7 +536,10 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
                 uint32_t pre[CPT];
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) pre[j] = d[j].mask;
-                accept_draws<CPT>(A, pre, rho, tile);
+                uint32_t ids[CPT];
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) ids[j] = tid * CPT + j;
+                accept_draws<CPT>(A, pre, ids, rho, tile);
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) d[j].mask = pre[j];
             }
@@ -553,7 +559,10 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
             pre[j] = da[j].ur >> 2;
         }
         if (ACCEPT) {
-            accept_draws<CPT>(A, pre, 0u, tile);
+            uint32_t ids[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) ids[j] = tid * CPT + j;
+            accept_draws<CPT>(A, pre, ids, 0u, tile);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) da[j].ur = pre[j] | (da[j].ur & 3u);
         }
@@ -567,6 +576,153 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
         }
     }
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
+}
+
+// DB device step with each lane holding a column of CPT vertically stacked
+// cells: lane t owns the cells (t mod ncx, CPT (t / ncx) + j), j = 0 .. CPT-1
+// (needs cells = lanes x CPT, CPT >= 2 and at most 64 cells per row, so a
+// wave holds whole rows of lanes).  The attempts, their random draws (keyed by
+// cell id) and the delayed-border order are those of sweep_tile; only the
+// bookkeeping differs.  Each round every cell draws its own attempt, except
+// the top cell of each column, which is drawn one round ahead and published
+// in LDS for the column above.  The dependency checks of the delayed borders
+// (does the attempt of the cell to the right / below sit on the site right of /
+// below mine?) read the cell below from the same lane (or, for the bottom
+// cell, the published top cell of the column below), and the cell to the
+// right from the neighbouring lane by a cross-lane permute.  A deferred
+// attempt is "remote" only in a bottom cell whose column below lies in
+// another wave, and only on the cell's bottom row; all others run in their
+// own wave right after the first pass (edges, then corners), remote ones
+// after the round's barrier, exactly as in db_round.
+template <bool ACCEPT, int CPT>
+__device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *smem, uint32_t tile)
+{
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    uint32_t *lds = smem;                                              // sx plane, then sy plane
+    uint32_t *orig = smem + A.NR * A.P + (A.NWX + 1u) * A.PY;          // edge blocks as loaded
+    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // 2 x NT published top-cell sites
+    uint32_t *flags = cpos + 2u * NT;                                  // 3 round flags
+
+    const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
+    const uint32_t X0 = (A.ox + 2u * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
+    const uint32_t Y0 = (A.oy + 2u * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
+    const uint32_t offx = X0 & 31u, offy = Y0 & 3u;
+
+    copy_window<true>(A, lds, orig, X0 >> 5, Y0 >> 2);
+
+    const uint32_t ncx = 1u << A.log2ncx;
+    const uint32_t cx = tid & (ncx - 1u), grp = tid >> A.log2ncx;
+    const uint32_t below_lane = (tid + ncx) & (NT - 1u);  // lane holding the column below
+    const bool border = (below_lane >> 6) != (tid >> 6);   // ... in another wave
+    const int rsrc = (int)((cx == ncx - 1u ? tid + 1u - ncx : tid + 1u) & 63u) << 2;  // lane of the column right
+    const uint32_t base_u = cx << A.log2Cx;
+    uint32_t cell[CPT], base_v[CPT];
+    uint32_t rw[CPT][4];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const uint32_t cy = grp * CPT + j;
+        cell[j] = (cy << A.log2ncx) | cx;
+        base_v[j] = cy << A.log2Cy;
+        rw[j][0] = rw[j][1] = rw[j][2] = rw[j][3] = 0u;
+    }
+    BlockDraw bd = {0u, 0u, 0u, 0u};
+
+    // the top cell's draw for round 0
+    uint32_t f16 = next_block_field(A, bd, 0u, tile);
+    CDraw top;
+    {
+        const uint32_t field = next_field(A, rw[0], 0u, cell[0], tile);
+        top = decode_db<ACCEPT>(A, field, f16, base_u, base_v[0]);
+        if (ACCEPT) {
+            uint32_t pre[1] = {top.ur >> 2};
+            const uint32_t ids[1] = {cell[0]};
+            accept_draws<1>(A, pre, ids, 0u, tile);
+            top.ur = pre[0] | (top.ur & 3u);
+        }
+        cpos[tid] = top.pos;
+    }
+    if (tid < 3) flags[tid] = 0u;
+    __syncthreads();
+
+    for (uint32_t rho = 0; rho < A.rounds; ++rho) {
+        // this round's attempts: the top cell's from the last round, the others drawn now
+        Draw d[CPT];
+        d[0] = expand<ACCEPT>(A, top, offx, offy);
+        {
+            uint32_t pre[CPT - 1], ids[CPT - 1];
+#pragma unroll
+            for (int j = 1; j < CPT; ++j) {
+                const uint32_t field = next_field(A, rw[j], rho, cell[j], tile);
+                d[j] = decode<kDB, ACCEPT>(A, field, f16, base_u, base_v[j], offx, offy);
+                pre[j - 1] = d[j].mask;
+                ids[j - 1] = cell[j];
+            }
+            if (ACCEPT) {
+                accept_draws<CPT - 1>(A, pre, ids, rho, tile);
+#pragma unroll
+                for (int j = 1; j < CPT; ++j) d[j].mask = pre[j - 1];
+            }
+        }
+        // the top cell's attempt of the next round, published for the column above
+        if (rho + 1u < A.rounds) {
+            f16 = next_block_field(A, bd, rho + 1u, tile);
+            const uint32_t field = next_field(A, rw[0], rho + 1u, cell[0], tile);
+            top = decode_db<ACCEPT>(A, field, f16, base_u, base_v[0]);
+            if (ACCEPT) {
+                uint32_t pre[1] = {top.ur >> 2};
+                const uint32_t ids[1] = {cell[0]};
+                accept_draws<1>(A, pre, ids, rho + 1u, tile);
+                top.ur = pre[0] | (top.ur & 3u);
+            }
+            cpos[((rho + 1u) & 1u) * NT + tid] = top.pos;
+        }
+        // order dependencies of the delayed borders
+        const uint32_t pbot = cpos[(rho & 1u) * NT + below_lane];
+        bool def[CPT], remote[CPT];
+        bool any1 = false, any2 = false;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)d[j].pos);
+            const uint32_t pd = j + 1 < CPT ? d[j + 1 < CPT ? j + 1 : j].pos : pbot;
+            const uint32_t rim = d[j].rim;
+            def[j] = ((rim & 1u) && pr == d[j].pos + 1u) || ((rim & 2u) && pd == d[j].pos + 0x10000u);
+            remote[j] = def[j] && j == CPT - 1 && border && (rim & 2u);
+            any1 |= remote[j] && rim != 3u;
+            any2 |= remote[j] && rim == 3u;
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) attempt(lds, d[j], !def[j]);
+        wave_order();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)  // deferred edges of this wave
+            if (def[j] && !remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+        wave_order();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
+            if (def[j] && !remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+        const uint64_t b1 = __ballot(any1), b2 = __ballot(any2);
+        if ((tid & 63u) == 0u && (b1 | b2)) atomicOr(&flags[rho % 3u], 1u);
+        if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
+        __syncthreads();
+        if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                if (remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+            wave_order();
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                if (remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+            __syncthreads();
+        }
+    }
+    copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
+}
+
+template <bool ACCEPT, int CPT>
+__global__ void __launch_bounds__(256) step_db_columns_kernel(StepArgs A)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_db_columns<ACCEPT, CPT>(A, smem, blockIdx.x);
 }
 
 // One device step of a single lattice: one workgroup per tile.  With more

@@ -30,19 +30,31 @@ int hip_fail(hipError_t e, const char *what)
 
 namespace {
 
-template <int SCHEME, bool ACCEPT, int CPT>
-int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
+// Launch one device-step kernel instance (LDS above 64 KiB needs the
+// attribute raised once per instance and process).
+template <typename Kernel>
+int launch_instance(Kernel *fn, uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
     if (lds > 64u * 1024u) {
-        static bool raised = false;  // once per kernel instance and process
+        static bool raised = false;
         if (!raised) {
-            HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&step_kernel<SCHEME, ACCEPT, CPT>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+            HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxLds));
             raised = true;
         }
     }
-    hipLaunchKernelGGL((step_kernel<SCHEME, ACCEPT, CPT>), dim3(ntiles), dim3(nt), lds, st, a);
+    hipLaunchKernelGGL(fn, dim3(ntiles), dim3(nt), lds, st, a);
     return OKPZ_OK;
+}
+
+// DB with at least two cells per lane and at most 64 cells per domain row
+// runs the column-mapped kernel (same results, less bookkeeping).
+template <int SCHEME, bool ACCEPT, int CPT>
+int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
+{
+    if (SCHEME == kDB && CPT >= 2 && (1u << a.log2ncx) <= 64u)
+        return launch_instance(&step_db_columns_kernel<ACCEPT, (CPT >= 2 ? CPT : 2)>, nt, ntiles, lds, st, a);
+    return launch_instance(&step_kernel<SCHEME, ACCEPT, CPT>, nt, ntiles, lds, st, a);
 }
 
 template <int SCHEME, bool ACCEPT>
