@@ -30,6 +30,36 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
 
+# HBM bytes per device-step launch of the benchmark workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one counter per run), scaled by
+# what the same counters read for the 4 GiB lattice copy in the same runs
+# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00); valid only for the device sources
+# they were taken on (hash of the files below).
+DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/okpz.hip",
+                  "paper_1705_01022_amd/csrc/philox.hpp", "paper_1705_01022_amd/csrc/internal.hpp")
+MEASURED_TRAFFIC = {"sources": "531ba5beb309c3be", "workload": "L131072",
+                    "fetch_kib": 798809.3, "write_kib": 1198080.0, "fetch_scale": 2.00, "write_scale": 1.00}
+
+
+def device_sources_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per step launch from the counters, or None if they were taken
+    on other sources or another workload."""
+    t = MEASURED_TRAFFIC
+    if workload != t["workload"] or device_sources_hash() != t["sources"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def ops_per_attempt(scheme: int, cell: int, accept: bool) -> float:
     """Algorithmic 32-bit VALU issue slots one update attempt needs (the design doc,
     "ALU roofline"): its share of a Philox4x32-10 block (100 slots: 10 rounds
@@ -281,6 +311,13 @@ def main():
     accept = not (p in (0.0, 1.0) and q in (0.0, 1.0))
     ops = ops_per_attempt(scheme, C, accept)
     alu_achieved = attempts_per_launch * ops / step_avg_s / 1e9
+    traffic = measured_traffic(args.workload)
+    cells = (D // C) * (D // C)
+    cpt = max(1, cells // 256)
+    if scheme == 1 and cpt >= 2 and D // C <= 64:
+        kernel_name = "step_db_columns_kernel<accept=%s, %d cells/lane> (%s)" % (accept, cpt, SCHEME_NAME[scheme])
+    else:
+        kernel_name = "step_kernel<%s, accept=%s, %d cells/lane>" % (SCHEME_NAME[scheme], accept, cpt)
     hbm_achieved = bytes_per_launch / step_avg_s / 1e9
     line = {
         "metric": "site-update attempts/s",
@@ -302,13 +339,15 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "step_kernel<%s>" % SCHEME_NAME[scheme],
+            "kernel": kernel_name,
             "bound": "alu",
             "achieved": alu_achieved,
             "peak": VALU_PEAK_GOPS,
             "unit": "Gop/s",
             "frac": alu_achieved / VALU_PEAK_GOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "B/launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+            "algorithmic_bytes_per_launch": bytes_per_launch,
             "ops_per_attempt": ops,
             "avg_launch_ms": step_avg_s * 1e3,
             "launches": tm["step_launches"],
