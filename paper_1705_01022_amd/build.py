@@ -24,6 +24,8 @@ COMPILE_FLAGS = [
     "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # let the rounds of one Philox block unroll fully in the DB step kernel
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -70,7 +70,9 @@ __device__ __forceinline__ uint32_t perm_element(uint32_t pick, uint32_t k)
     return e;
 }
 
-template <int SCHEME, int CPT>
+// COLS: every lattice of the launch is DB with lanes x CPT cells per domain
+// and at most 64 cells per row, so the column-mapped sweep serves them all.
+template <int SCHEME, int CPT, bool COLS>
 __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
 {
     extern __shared__ uint32_t smem[];
@@ -150,10 +152,17 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
         A.c3 = (uint32_t)(m << 2) | k;
         // the earlier steps' words, written by other workgroups, become visible
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (S.accept)
-            sweep_tile<SCHEME, true, CPT, false>(A, smem, tile);
-        else
-            sweep_tile<SCHEME, false, CPT, false>(A, smem, tile);
+        if constexpr (COLS) {
+            if (S.accept)
+                sweep_db_columns<true, CPT, 0>(A, smem, tile);
+            else
+                sweep_db_columns<false, CPT, 0>(A, smem, tile);
+        } else {
+            if (S.accept)
+                sweep_tile<SCHEME, true, CPT, false>(A, smem, tile);
+            else
+                sweep_tile<SCHEME, false, CPT, false>(A, smem, tile);
+        }
         // publish this tile's words before counting the item as done
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
@@ -273,22 +282,31 @@ int grow_tables(okpz_batch *b, size_t nslots, size_t nphases)
     return OKPZ_OK;
 }
 
-template <int SCHEME, int CPT>
+template <int SCHEME, int CPT, bool COLS>
 const void *batch_fn()
 {
-    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT>);
+    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT, COLS>);
 }
 
-const void *batch_kernel_for(int scheme, uint32_t cpt)
+const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols)
 {
 #define OKPZ_BATCH_CASES(S)                          \
     switch (cpt) {                                   \
-    case 1: return batch_fn<S, 1>();                 \
-    case 2: return batch_fn<S, 2>();                 \
-    case 4: return batch_fn<S, 4>();                 \
-    case 8: return batch_fn<S, 8>();                 \
-    case 16: return batch_fn<S, 16>();               \
+    case 1: return batch_fn<S, 1, false>();          \
+    case 2: return batch_fn<S, 2, false>();          \
+    case 4: return batch_fn<S, 4, false>();          \
+    case 8: return batch_fn<S, 8, false>();          \
+    case 16: return batch_fn<S, 16, false>();        \
     default: return nullptr;                         \
+    }
+    if (cols && scheme == kDB) {
+        switch (cpt) {
+        case 2: return batch_fn<kDB, 2, true>();
+        case 4: return batch_fn<kDB, 4, true>();
+        case 8: return batch_fn<kDB, 8, true>();
+        case 16: return batch_fn<kDB, 16, true>();
+        default: break;
+        }
     }
     switch (scheme) {
     case kDT: OKPZ_BATCH_CASES(kDT)
@@ -434,13 +452,24 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return n_mcs[a] > n_mcs[c]; });
     const uint32_t n = (uint32_t)order.size();
 
-    // launch shape: lanes per workgroup, cells per lane (largest domain)
-    const uint32_t nt = b->threads ? b->threads : 256u;
+    // launch shape: lanes per workgroup (default: enough for the largest
+    // domain's cells, 64 .. 256), cells per lane
     uint32_t max_cells = 1;
     for (int32_t s : order) max_cells = std::max(max_cells, cells_of(b->slots[s]->prm));
+    uint32_t nt = b->threads;
+    if (nt == 0) {
+        nt = 64;
+        while (nt < 256u && nt < max_cells) nt *= 2;
+    }
     uint32_t cpt = 1;
     while (cpt * nt < max_cells) cpt *= 2;
     if (cpt > 16) return OKPZ_EINVAL;
+    // DB lattices that all fill the workgroup exactly take the column-mapped sweep
+    bool cols = b->scheme == kDB && cpt >= 2;
+    for (int32_t s : order) {
+        const okpz_params &prm = b->slots[s]->prm;
+        cols = cols && cells_of(prm) == nt * cpt && prm.dom_x / prm.cell_x <= 64u;
+    }
 
     // tables
     std::vector<BatchSlot> slots(n);
@@ -492,7 +521,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     }
     const uint32_t nphase = (uint32_t)phases.size() - 1;
 
-    const void *fn = batch_kernel_for(b->scheme, cpt);
+    const void *fn = batch_kernel_for(b->scheme, cpt, cols);
     if (!fn) return OKPZ_EINVAL;
     if (lds > 64u * 1024u)
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLds - kStaticLds)));
@@ -517,7 +546,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         k += sizeof(uint32_t) * (n + 1);
         std::memcpy(k, phases.data(), sizeof(BatchPhase) * phases.size());
         k += sizeof(BatchPhase) * phases.size();
-        const uint32_t shape[4] = {nt, cpt, grid, b->use_graph ? 1u : 0u};
+        const uint32_t shape[4] = {nt, cpt | (cols ? 0x100u : 0u), grid, b->use_graph ? 1u : 0u};
         std::memcpy(k, shape, sizeof(shape));
     }
     std::vector<int32_t> table_slot(order.begin(), order.end());

@@ -594,7 +594,116 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
 // another wave, and only on the cell's bottom row; all others run in their
 // own wave right after the first pass (edges, then corners), remote ones
 // after the round's barrier, exactly as in db_round.
+// One round of the column-mapped DB sweep.  field[j], j >= 1: the lane-draw
+// fields of round rho; field[0]: the top cell's field of round rho + 1
+// (has_next), drawn with the block field f16_next and published.
 template <bool ACCEPT, int CPT>
+__device__ __forceinline__ void db_columns_round(const StepArgs &A, uint32_t *lds, uint32_t *cpos, uint32_t *flags,
+                                                 CDraw &top, const uint32_t (&field)[CPT], uint32_t f16,
+                                                 uint32_t f16_next, bool has_next, uint32_t rho, uint32_t tile,
+                                                 uint32_t offx, uint32_t offy, uint32_t base_u,
+                                                 const uint32_t (&base_v)[CPT], const uint32_t (&cell)[CPT],
+                                                 uint32_t below_lane, bool border, int rsrc)
+{
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    // this round's attempts: the top cell's from the last round, the others drawn now
+    Draw d[CPT];
+    d[0] = expand<ACCEPT>(A, top, offx, offy);
+    {
+        uint32_t pre[CPT - 1], ids[CPT - 1];
+#pragma unroll
+        for (int j = 1; j < CPT; ++j) {
+            d[j] = decode<kDB, ACCEPT>(A, field[j], f16, base_u, base_v[j], offx, offy);
+            pre[j - 1] = d[j].mask;
+            ids[j - 1] = cell[j];
+        }
+        if (ACCEPT) {
+            accept_draws<CPT - 1>(A, pre, ids, rho, tile);
+#pragma unroll
+            for (int j = 1; j < CPT; ++j) d[j].mask = pre[j - 1];
+        }
+    }
+    // the top cell's attempt of the next round, published for the column above
+    if (has_next) {
+        top = decode_db<ACCEPT>(A, field[0], f16_next, base_u, base_v[0]);
+        if (ACCEPT) {
+            uint32_t pre[1] = {top.ur >> 2};
+            const uint32_t ids[1] = {cell[0]};
+            accept_draws<1>(A, pre, ids, rho + 1u, tile);
+            top.ur = pre[0] | (top.ur & 3u);
+        }
+        cpos[((rho + 1u) & 1u) * NT + tid] = top.pos;
+    }
+    // order dependencies of the delayed borders
+    const uint32_t pbot = cpos[(rho & 1u) * NT + below_lane];
+    bool def[CPT], remote[CPT];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)d[j].pos);
+        const uint32_t pd = j + 1 < CPT ? d[j + 1 < CPT ? j + 1 : j].pos : pbot;
+        const uint32_t rim = d[j].rim;
+        def[j] = ((rim & 1u) && pr == d[j].pos + 1u) || ((rim & 2u) && pd == d[j].pos + 0x10000u);
+        remote[j] = def[j] && j == CPT - 1 && border && (rim & 2u);
+        any |= remote[j];
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) attempt(lds, d[j], !def[j]);
+    wave_order();
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)  // deferred edges of this wave
+        if (def[j] && !remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+    wave_order();
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
+        if (def[j] && !remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+    const uint64_t wave_any = __ballot(any);  // every lane takes part in the ballot
+    if ((tid & 63u) == 0u && wave_any) atomicOr(&flags[rho % 3u], 1u);
+    if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
+    __syncthreads();
+    if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+        wave_order();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            if (remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+        __syncthreads();
+    }
+}
+
+// Field k (0 .. 128/F - 1) of a Philox block w, F = 2^FL bits, lowest first.
+template <int FL>
+__device__ __forceinline__ uint32_t block_field(const uint32_t (&w)[4], int k)
+{
+    constexpr int F = 1 << FL, FPW = 32 / F;
+    if (F == 32) return w[k];
+    return (w[k / FPW] >> (F * (k % FPW))) & ((1u << (F & 31)) - 1u);
+}
+
+// DB device step with each lane holding a column of CPT vertically stacked
+// cells: lane t owns the cells (t mod ncx, CPT (t / ncx) + j), j = 0 .. CPT-1
+// (needs cells = lanes x CPT, CPT >= 2 and at most 64 cells per row, so a
+// wave holds whole rows of lanes).  The attempts, their random draws (keyed by
+// cell id) and the delayed-border order are those of sweep_tile; only the
+// bookkeeping differs.  Each round every cell draws its own attempt, except
+// the top cell of each column, which is drawn one round ahead and published
+// in LDS for the column above.  The dependency checks of the delayed borders
+// (does the attempt of the cell to the right / below sit on the site right of /
+// below mine?) read the cell below from the same lane (or, for the bottom
+// cell, the published top cell of the column below), and the cell to the
+// right from the neighbouring lane by a cross-lane permute.  A deferred
+// attempt is "remote" only in a bottom cell whose column below lies in
+// another wave, and only on the cell's bottom row; all others run in their
+// own wave right after the first pass (edges, then corners), remote ones
+// after the round's barrier, exactly as in db_round.
+//
+// FL > 0: the lane-draw field width is 2^FL bits (known at compile time) and
+// the rounds are a multiple of the 128 / 2^FL fields of one Philox block; the
+// rounds of one block are unrolled, so every field is a fixed shift of a
+// fixed word.  FL = 0: the width is taken from A at run time.
+template <bool ACCEPT, int CPT, int FL>
 __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *smem, uint32_t tile)
 {
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
@@ -617,21 +726,16 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
     const int rsrc = (int)((cx == ncx - 1u ? tid + 1u - ncx : tid + 1u) & 63u) << 2;  // lane of the column right
     const uint32_t base_u = cx << A.log2Cx;
     uint32_t cell[CPT], base_v[CPT];
-    uint32_t rw[CPT][4];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const uint32_t cy = grp * CPT + j;
         cell[j] = (cy << A.log2ncx) | cx;
         base_v[j] = cy << A.log2Cy;
-        rw[j][0] = rw[j][1] = rw[j][2] = rw[j][3] = 0u;
     }
     BlockDraw bd = {0u, 0u, 0u, 0u};
-
-    // the top cell's draw for round 0
     uint32_t f16 = next_block_field(A, bd, 0u, tile);
     CDraw top;
-    {
-        const uint32_t field = next_field(A, rw[0], 0u, cell[0], tile);
+    auto draw_top0 = [&](uint32_t field) {  // the top cell's draw for round 0
         top = decode_db<ACCEPT>(A, field, f16, base_u, base_v[0]);
         if (ACCEPT) {
             uint32_t pre[1] = {top.ur >> 2};
@@ -640,89 +744,78 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
             top.ur = pre[0] | (top.ur & 3u);
         }
         cpos[tid] = top.pos;
-    }
-    if (tid < 3) flags[tid] = 0u;
-    __syncthreads();
+        if (tid < 3) flags[tid] = 0u;
+        __syncthreads();
+    };
 
-    for (uint32_t rho = 0; rho < A.rounds; ++rho) {
-        // this round's attempts: the top cell's from the last round, the others drawn now
-        Draw d[CPT];
-        d[0] = expand<ACCEPT>(A, top, offx, offy);
+    if constexpr (FL == 0) {
+        uint32_t rw[CPT][4];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) rw[j][0] = rw[j][1] = rw[j][2] = rw[j][3] = 0u;
+        draw_top0(next_field(A, rw[0], 0u, cell[0], tile));
+        for (uint32_t rho = 0; rho < A.rounds; ++rho) {
+            uint32_t field[CPT];
+#pragma unroll
+            for (int j = 1; j < CPT; ++j) field[j] = next_field(A, rw[j], rho, cell[j], tile);
+            const bool has_next = rho + 1u < A.rounds;
+            uint32_t f16n = 0u;
+            field[0] = 0u;
+            if (has_next) {
+                f16n = next_block_field(A, bd, rho + 1u, tile);
+                field[0] = next_field(A, rw[0], rho + 1u, cell[0], tile);
+            }
+            db_columns_round<ACCEPT, CPT>(A, lds, cpos, flags, top, field, f16, f16n, has_next, rho, tile, offx,
+                                          offy, base_u, base_v, cell, below_lane, border, rsrc);
+            f16 = f16n;
+        }
+    } else {
+        constexpr int RPB = 128 >> FL;  // rounds per Philox block
+        uint32_t w0[4];                 // the top cell's current block
         {
-            uint32_t pre[CPT - 1], ids[CPT - 1];
+            const u32x4 r = philox4x32_10(A.key0, A.key1, 0u, cell[0], tile, A.c3);
+            w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
+        }
+        draw_top0(block_field<FL>(w0, 0));
+        const uint32_t nblk = A.rounds / RPB;
+        for (uint32_t blk = 0; blk < nblk; ++blk) {
+            uint32_t w[CPT][4];
 #pragma unroll
             for (int j = 1; j < CPT; ++j) {
-                const uint32_t field = next_field(A, rw[j], rho, cell[j], tile);
-                d[j] = decode<kDB, ACCEPT>(A, field, f16, base_u, base_v[j], offx, offy);
-                pre[j - 1] = d[j].mask;
-                ids[j - 1] = cell[j];
+                const u32x4 r = philox4x32_10(A.key0, A.key1, blk, cell[j], tile, A.c3);
+                w[j][0] = r.x; w[j][1] = r.y; w[j][2] = r.z; w[j][3] = r.w;
             }
-            if (ACCEPT) {
-                accept_draws<CPT - 1>(A, pre, ids, rho, tile);
 #pragma unroll
-                for (int j = 1; j < CPT; ++j) d[j].mask = pre[j - 1];
+            for (int k = 0; k < RPB; ++k) {
+                const uint32_t rho = blk * RPB + k;
+                uint32_t field[CPT];
+#pragma unroll
+                for (int j = 1; j < CPT; ++j) field[j] = block_field<FL>(w[j], k);
+                const bool has_next = rho + 1u < A.rounds;
+                uint32_t f16n = 0u;
+                if (k == RPB - 1) {
+                    if (has_next) {
+                        const u32x4 r = philox4x32_10(A.key0, A.key1, blk + 1u, cell[0], tile, A.c3);
+                        w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
+                    }
+                    field[0] = block_field<FL>(w0, 0);
+                } else {
+                    field[0] = block_field<FL>(w0, k + 1 < RPB ? k + 1 : 0);
+                }
+                if (has_next) f16n = next_block_field(A, bd, rho + 1u, tile);
+                db_columns_round<ACCEPT, CPT>(A, lds, cpos, flags, top, field, f16, f16n, has_next, rho, tile, offx,
+                                              offy, base_u, base_v, cell, below_lane, border, rsrc);
+                f16 = f16n;
             }
-        }
-        // the top cell's attempt of the next round, published for the column above
-        if (rho + 1u < A.rounds) {
-            f16 = next_block_field(A, bd, rho + 1u, tile);
-            const uint32_t field = next_field(A, rw[0], rho + 1u, cell[0], tile);
-            top = decode_db<ACCEPT>(A, field, f16, base_u, base_v[0]);
-            if (ACCEPT) {
-                uint32_t pre[1] = {top.ur >> 2};
-                const uint32_t ids[1] = {cell[0]};
-                accept_draws<1>(A, pre, ids, rho + 1u, tile);
-                top.ur = pre[0] | (top.ur & 3u);
-            }
-            cpos[((rho + 1u) & 1u) * NT + tid] = top.pos;
-        }
-        // order dependencies of the delayed borders
-        const uint32_t pbot = cpos[(rho & 1u) * NT + below_lane];
-        bool def[CPT], remote[CPT];
-        bool any1 = false, any2 = false;
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)d[j].pos);
-            const uint32_t pd = j + 1 < CPT ? d[j + 1 < CPT ? j + 1 : j].pos : pbot;
-            const uint32_t rim = d[j].rim;
-            def[j] = ((rim & 1u) && pr == d[j].pos + 1u) || ((rim & 2u) && pd == d[j].pos + 0x10000u);
-            remote[j] = def[j] && j == CPT - 1 && border && (rim & 2u);
-            any1 |= remote[j] && rim != 3u;
-            any2 |= remote[j] && rim == 3u;
-        }
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) attempt(lds, d[j], !def[j]);
-        wave_order();
-#pragma unroll
-        for (int j = 0; j < CPT; ++j)  // deferred edges of this wave
-            if (def[j] && !remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
-        wave_order();
-#pragma unroll
-        for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
-            if (def[j] && !remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
-        const uint64_t b1 = __ballot(any1), b2 = __ballot(any2);
-        if ((tid & 63u) == 0u && (b1 | b2)) atomicOr(&flags[rho % 3u], 1u);
-        if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
-        __syncthreads();
-        if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
-#pragma unroll
-            for (int j = 0; j < CPT; ++j)
-                if (remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
-            wave_order();
-#pragma unroll
-            for (int j = 0; j < CPT; ++j)
-                if (remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
-            __syncthreads();
         }
     }
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
 }
 
-template <bool ACCEPT, int CPT>
+template <bool ACCEPT, int CPT, int FL>
 __global__ void __launch_bounds__(256) step_db_columns_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];
-    sweep_db_columns<ACCEPT, CPT>(A, smem, blockIdx.x);
+    sweep_db_columns<ACCEPT, CPT, FL>(A, smem, blockIdx.x);
 }
 
 // One device step of a single lattice: one workgroup per tile.  With more

@@ -52,8 +52,18 @@ int launch_instance(Kernel *fn, uint32_t nt, uint32_t ntiles, size_t lds, hipStr
 template <int SCHEME, bool ACCEPT, int CPT>
 int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
-    if (SCHEME == kDB && CPT >= 2 && (1u << a.log2ncx) <= 64u)
-        return launch_instance(&step_db_columns_kernel<ACCEPT, (CPT >= 2 ? CPT : 2)>, nt, ntiles, lds, st, a);
+    if constexpr (SCHEME == kDB && CPT >= 2) {
+        if ((1u << a.log2ncx) <= 64u) {
+            // the common field widths (16 bits with acceptance draws, 8 without)
+            // with whole Philox blocks per domain sweep take the unrolled variant
+            constexpr int FL = ACCEPT ? 4 : 3;
+            if constexpr (CPT <= 8) {
+                if (a.F_log2 == (uint32_t)FL && a.rounds % (128u >> FL) == 0u)
+                    return launch_instance(&step_db_columns_kernel<ACCEPT, CPT, FL>, nt, ntiles, lds, st, a);
+            }
+            return launch_instance(&step_db_columns_kernel<ACCEPT, CPT, 0>, nt, ntiles, lds, st, a);
+        }
+    }
     return launch_instance(&step_kernel<SCHEME, ACCEPT, CPT>, nt, ntiles, lds, st, a);
 }
 

@@ -144,3 +144,17 @@ def test_batch_rejects_bad_arguments(okpz):
     b.run([], [], [])                              # nothing to do
     b.close()
     other.close()
+
+
+@pytest.mark.parametrize("threads", [64, 128, 0])
+def test_batch_db_column_sweep(okpz, orc, threads):
+    """DB lattices whose domains all hold lanes x cells-per-lane cells take the
+    column-mapped sweep (64 or 128 lanes here; the default width takes the
+    generic one): same results."""
+    mix = [(128, 64, 4, 0.95, 0.05, 3), (256, 64, 4, 1.0, 0.0, 2), (128, 64, 4, 0.6, 0.4, 4),
+           (256, 128, 8, 0.8, 0.3, 2)]
+    b, lats, mirrors = make_batch(okpz, orc, 1, mix)
+    b.config(threads, 0, True)
+    run_both(b, lats, mirrors, mix, [m[5] for m in mix])
+    run_both(b, lats, mirrors, mix, [1, 2, 1, 1])
+    b.close()
