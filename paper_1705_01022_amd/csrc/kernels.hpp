@@ -634,7 +634,19 @@ __device__ __forceinline__ void db_columns_round(const StepArgs &A, uint32_t *ld
         }
         cpos[((rho + 1u) & 1u) * NT + tid] = top.pos;
     }
-    // order dependencies of the delayed borders
+    // Order dependencies of the delayed borders: the attempt of the cell to
+    // the right sits on the site right of mine, or the one of the cell below
+    // on the site below mine.  Either implies that mine lies on my cell's
+    // right column / bottom row (the neighbouring cell's sites can touch mine
+    // only there; a site one past the domain edge is never a neighbour's), so
+    // the rim needs no separate test; it is worked out only for deferred
+    // attempts (a corner goes after the edges).
+    const uint32_t cxm = (1u << A.log2Cx) - 1u, cym = (1u << A.log2Cy) - 1u;
+    const uint32_t shx = (f16 >> 2) & cxm, shy = (f16 >> 8) & cym;  // this round's cell-grid shift
+    auto bottom_row = [&](int j) { return (((d[j].pos >> 16) - shy - base_v[j]) & (A.Dy - 1u)) == cym; };
+    auto corner = [&](int j) {
+        return bottom_row(j) && (((d[j].pos & 0xFFFFu) - shx - base_u) & (A.Dx - 1u)) == cxm;
+    };
     const uint32_t pbot = cpos[(rho & 1u) * NT + below_lane];
     bool def[CPT], remote[CPT];
     bool any = false;
@@ -642,33 +654,36 @@ __device__ __forceinline__ void db_columns_round(const StepArgs &A, uint32_t *ld
     for (int j = 0; j < CPT; ++j) {
         const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)d[j].pos);
         const uint32_t pd = j + 1 < CPT ? d[j + 1 < CPT ? j + 1 : j].pos : pbot;
-        const uint32_t rim = d[j].rim;
-        def[j] = ((rim & 1u) && pr == d[j].pos + 1u) || ((rim & 2u) && pd == d[j].pos + 0x10000u);
-        remote[j] = def[j] && j == CPT - 1 && border && (rim & 2u);
+        def[j] = pr == d[j].pos + 1u || pd == d[j].pos + 0x10000u;
+        // remote: a bottom-row attempt of a bottom cell whose column below is in another wave
+        remote[j] = j == CPT - 1 && border && def[j] && bottom_row(j);
         any |= remote[j];
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) attempt(lds, d[j], !def[j]);
     wave_order();
+    bool cor[CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)  // deferred edges of this wave
-        if (def[j] && !remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+    for (int j = 0; j < CPT; ++j) {  // deferred edges of this wave
+        cor[j] = false;
+        if (def[j] && !remote[j]) {
+            cor[j] = corner(j);
+            if (!cor[j]) attempt(lds, d[j]);
+        }
+    }
     wave_order();
 #pragma unroll
     for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
-        if (def[j] && !remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+        if (def[j] && !remote[j] && cor[j]) attempt(lds, d[j]);
     const uint64_t wave_any = __ballot(any);  // every lane takes part in the ballot
     if ((tid & 63u) == 0u && wave_any) atomicOr(&flags[rho % 3u], 1u);
     if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
     __syncthreads();
     if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
-#pragma unroll
-        for (int j = 0; j < CPT; ++j)
-            if (remote[j] && d[j].rim != 3u) attempt(lds, d[j]);
+        const bool rc = remote[CPT - 1] && corner(CPT - 1);
+        if (remote[CPT - 1] && !rc) attempt(lds, d[CPT - 1]);
         wave_order();
-#pragma unroll
-        for (int j = 0; j < CPT; ++j)
-            if (remote[j] && d[j].rim == 3u) attempt(lds, d[j]);
+        if (rc) attempt(lds, d[CPT - 1]);
         __syncthreads();
     }
 }
