@@ -150,8 +150,10 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
         A.set_a = set & 1u;
         A.set_b = set >> 1;
         A.c3 = (uint32_t)(m << 2) | k;
-        // the earlier steps' words, written by other workgroups, become visible
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // Visibility of the earlier steps' words, written by other workgroups:
+        // thread 0 took the agent-scope acquire after its wait, before the
+        // barrier above (it invalidates the caches this workgroup reads through,
+        // which all its waves share).
         if constexpr (COLS) {
             if (S.accept)
                 sweep_db_columns<true, CPT, 0>(A, smem, tile);
@@ -163,8 +165,11 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
             else
                 sweep_tile<SCHEME, false, CPT, false>(A, smem, tile);
         }
-        // publish this tile's words before counting the item as done
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // Publish this tile's words before counting the item as done: every
+        // lane waits until its own stores are acknowledged, the barrier orders
+        // them before thread 0, whose agent-scope release increment writes them
+        // back for the other dies (once per item, not once per wave).
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) __hip_atomic_fetch_add(&B.done[my_slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
