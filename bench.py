@@ -170,6 +170,17 @@ def batched_comparison(okpz, n_batched=200, n_plain=4, tune_mcs=10):
     el_b = time.perf_counter() - t0
     gpu_ms = b.get_timing()["ms"]
     b.timing(False)
+    # measuring the whole ensemble: one batched pass (W^2, C_h, C_s of every
+    # member in three launches) against one pass per member
+    b.snapshot()
+    b.observe(with_autocorr=True)  # warm-up
+    t0 = time.perf_counter()
+    b.observe(with_autocorr=True)
+    el_ob = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.observe(with_autocorr=True)
+    el_ol = time.perf_counter() - t0
     t0 = time.perf_counter()
     for lat, c in zip(lats, comp):
         lat.run(n_plain, c.p, c.q)
@@ -185,7 +196,8 @@ def batched_comparison(okpz, n_batched=200, n_plain=4, tune_mcs=10):
             "batched_kernel_ms": gpu_ms, "plain_attempts_per_s": plain, "plain_mcs": n_plain,
             "batched_over_plain": batched / plain,
             "launch_shape": {"threads": best[0], "grid_fraction": best[1], "graph": best[2]},
-            "tuner_ms": {"%d/%.2f/%s" % k: v for k, v in tuned["times_ms"].items()}}
+            "tuner_ms": {"%d/%.2f/%s" % k: v for k, v in tuned["times_ms"].items()},
+            "observe_all_ms": {"batched": 1e3 * el_ob, "per_member": 1e3 * el_ol}}
 
 
 def _serve_window(okpz, reqs, time_scale=1.0, chunk_mcs=64):

@@ -215,6 +215,26 @@ int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out);
  */
 int okpz_observe(okpz_lattice *lat, okpz_moments *moments, okpz_correlation *corr);
 
+/*
+ * Checkpoint and resume.  okpz_save writes the lattice state (and, if
+ * with_snapshot, the snapshot of okpz_snapshot with its time s) to host_buf
+ * as a self-describing blob of okpz_checkpoint_size bytes: a 128-byte header
+ * (magic, format version, the lattice parameters, MCS count, word count and
+ * a 64-bit checksum) followed by the words in the device layout.  The caller
+ * owns the buffer.  okpz_load restores such a blob into a lattice created
+ * with the same parameters (all okpz_params fields equal, seed and stream
+ * included, so that the resumed run draws the same random numbers as an
+ * uninterrupted one): the state, the MCS count and, when saved, the snapshot.
+ * EINVAL for a short buffer, another format or version, other parameters, a
+ * checksum mismatch or a state that is not a height configuration (a slope
+ * plaquette that does not close, or nonzero slope sums along row 0 or
+ * column 0); the lattice is unchanged then.  ESTATE: with_snapshot without a
+ * snapshot.  Both synchronous.
+ */
+int okpz_checkpoint_size(const okpz_lattice *lat, int with_snapshot, size_t *nbytes);
+int okpz_save(okpz_lattice *lat, int with_snapshot, void *host_buf, size_t nbytes);
+int okpz_load(okpz_lattice *lat, const void *host_buf, size_t nbytes);
+
 /* Copy the state to host `sites` (L*L bytes).  Synchronous. */
 int okpz_get_sites(okpz_lattice *lat, uint8_t *sites);
 
@@ -351,6 +371,36 @@ int okpz_batch_sync(okpz_batch *batch);
  * returns total milliseconds, launches and update attempts since enabled. */
 int okpz_batch_timing(okpz_batch *batch, int enable);
 int okpz_batch_get_timing(okpz_batch *batch, double *ms, uint64_t *launches, uint64_t *attempts);
+
+/*
+ * Observables of every member at once: the exact height moments W^2 and
+ * W^2_sub (Eq. `eq:Wdef`, as okpz_measure) into moments[s] and, if corr is
+ * not NULL, C_h(t, s) (Eq. `eq:kpz_ac_C`) and C_s against each member's snapshot
+ * into corr[s], for every slot s < okpz_batch_size (free slots are zeroed).
+ * Three launches for the whole batch (anchors, band moments, exact totals),
+ * whatever the number of members; values are identical to okpz_observe on
+ * each member.  Synchronous.  OKPZ_ESTATE if corr is given and a member has
+ * no snapshot; OKPZ_EWAIT after a failed batch launch.
+ */
+int okpz_batch_observe(okpz_batch *batch, okpz_moments *moments, okpz_correlation *corr);
+
+/* Snapshot of every member (as okpz_snapshot on each: the reference time s
+ * of C_h(t, s)), in one copy launch plus the measurement launches.
+ * Synchronous. */
+int okpz_batch_snapshot(okpz_batch *batch);
+
+/*
+ * A measured series: for i = 0 .. n_times-1, advance every member to
+ * times[i] MCS past its count at the call (times non-decreasing; rates
+ * p[s], q[s] as in okpz_batch_run) and observe all members there:
+ * moments[i * nslots + s] and, if corr is not NULL, corr[i * nslots + s]
+ * (nslots = okpz_batch_size).  The log-spaced measurement times of the
+ * roughness and autocorrelation curves (Sec. 2.1, Sec. 4.2) for a whole
+ * ensemble of realisations.  Validates everything first (EINVAL, EOVERFLOW,
+ * ESTATE without snapshots when corr is given).  Synchronous.
+ */
+int okpz_batch_series(okpz_batch *batch, const uint64_t *times, size_t n_times, const double *p, const double *q,
+                      okpz_moments *moments, okpz_correlation *corr);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.  Requests (lattice

@@ -143,6 +143,9 @@ _SIGS = {
     "okpz_autocorr": (ctypes.c_int, [_P, ctypes.POINTER(Correlation)]),
     "okpz_observe": (ctypes.c_int, [_P, ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
     "okpz_get_sites": (ctypes.c_int, [_P, _P]),
+    "okpz_checkpoint_size": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "okpz_save": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t]),
+    "okpz_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "okpz_get_window": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint32, _P]),
     "okpz_set_window": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -168,6 +171,10 @@ _SIGS = {
     "okpz_batch_config": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
     "okpz_batch_run": (ctypes.c_int, [_P, _P, _P, _P]),
     "okpz_batch_sync": (ctypes.c_int, [_P]),
+    "okpz_batch_observe": (ctypes.c_int, [_P, ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
+    "okpz_batch_snapshot": (ctypes.c_int, [_P]),
+    "okpz_batch_series": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P,
+                                          ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
     "okpz_batch_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "okpz_batch_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_uint64),
@@ -311,26 +318,14 @@ class Lattice:
     def measure(self) -> dict:
         m = Moments()
         _check(load().okpz_measure(self._h, ctypes.byref(m)), "okpz_measure")
-        return {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
-                "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
-                "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
-                "w2": m.w2, "w2_sub": m.w2_sub}
+        return _moments_dict(m)
 
     def observe(self, with_autocorr: bool = True):
         """Moments and (optionally) C_h from one pass; returns (moments, corr or None)."""
         m, c = Moments(), Correlation()
         _check(load().okpz_observe(self._h, ctypes.byref(m), ctypes.byref(c) if with_autocorr else None),
                "okpz_observe")
-        mo = {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
-              "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
-              "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
-              "w2": m.w2, "w2_sub": m.w2_sub}
-        ac = None
-        if with_autocorr:
-            ac = {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
-                  "s1_s": _to_int(c.s1_s), "c_h": c.c_h,
-                  "overlap": c.overlap, "c_s": c.c_s}
-        return mo, ac
+        return _moments_dict(m), (_corr_dict(c) if with_autocorr else None)
 
     def snapshot(self):
         _check(load().okpz_snapshot(self._h), "okpz_snapshot")
@@ -338,9 +333,23 @@ class Lattice:
     def autocorr(self) -> dict:
         c = Correlation()
         _check(load().okpz_autocorr(self._h, ctypes.byref(c)), "okpz_autocorr")
-        return {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
-                "s1_s": _to_int(c.s1_s), "c_h": c.c_h,
-                  "overlap": c.overlap, "c_s": c.c_s}
+        return _corr_dict(c)
+
+    # -- checkpoint / resume
+    def save(self, with_snapshot: bool = False) -> np.ndarray:
+        """The state (and snapshot) as a checkpoint blob (uint8 array)."""
+        n = ctypes.c_size_t()
+        _check(load().okpz_checkpoint_size(self._h, int(with_snapshot), ctypes.byref(n)), "okpz_checkpoint_size")
+        out = np.empty(n.value, dtype=np.uint8)
+        _check(load().okpz_save(self._h, int(with_snapshot), _ptr(out), out.size), "okpz_save")
+        return out
+
+    def load(self, blob):
+        """Restore a checkpoint written by :meth:`save` of a lattice with the
+        same parameters."""
+        b = np.ascontiguousarray(np.frombuffer(blob, dtype=np.uint8) if isinstance(blob, (bytes, bytearray))
+                                 else blob, dtype=np.uint8)
+        _check(load().okpz_load(self._h, _ptr(b), b.size), "okpz_load")
 
     # -- export / import
     def sites(self) -> np.ndarray:
@@ -385,6 +394,18 @@ class Lattice:
                                       ctypes.byref(mn)), "okpz_get_timing")
         return {"step_ms": sm.value, "step_launches": sn.value,
                 "measure_ms": mm.value, "measure_launches": mn.value}
+
+
+def _moments_dict(m) -> dict:
+    return {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
+            "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
+            "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
+            "w2": m.w2, "w2_sub": m.w2_sub}
+
+
+def _corr_dict(c) -> dict:
+    return {"t": c.t, "s": c.s, "s_ts": _to_int(c.s_ts), "s1_t": _to_int(c.s1_t),
+            "s1_s": _to_int(c.s1_s), "c_h": c.c_h, "overlap": c.overlap, "c_s": c.c_s}
 
 
 class Batch:
@@ -459,6 +480,47 @@ class Batch:
 
     def sync(self):
         _check(load().okpz_batch_sync(self._h), "okpz_batch_sync")
+
+    def _rates(self, p, q):
+        n = self.size
+        pp = np.zeros(n, dtype=np.float64)
+        qq = np.zeros(n, dtype=np.float64)
+        for arr, src in ((pp, p), (qq, q)):
+            if isinstance(src, dict):
+                for k, v in src.items():
+                    arr[k] = v
+            elif np.isscalar(src):
+                arr[[k for k in self.members]] = src
+            else:
+                arr[:len(src)] = src
+        return pp, qq
+
+    def snapshot(self):
+        """Snapshot of every member (reference time s of C_h(t, s))."""
+        _check(load().okpz_batch_snapshot(self._h), "okpz_batch_snapshot")
+
+    def observe(self, with_autocorr: bool = False) -> dict:
+        """Moments (and C_h, C_s against the snapshots) of every member in
+        three launches: {slot: (moments, corr or None)}."""
+        n = self.size
+        m = (Moments * max(n, 1))()
+        c = (Correlation * max(n, 1))() if with_autocorr else None
+        _check(load().okpz_batch_observe(self._h, m, c), "okpz_batch_observe")
+        return {s: (_moments_dict(m[s]), _corr_dict(c[s]) if with_autocorr else None) for s in self.members}
+
+    def series(self, times, p, q, with_autocorr: bool = False) -> list:
+        """Advance every member to each of ``times`` (MCS from now, non-
+        decreasing) and observe all members there; one entry per time:
+        {slot: (moments, corr or None)}."""
+        n = self.size
+        t = np.ascontiguousarray(times, dtype=np.uint64)
+        pp, qq = self._rates(p, q)
+        k = len(t)
+        m = (Moments * max(n * k, 1))()
+        c = (Correlation * max(n * k, 1))() if with_autocorr else None
+        _check(load().okpz_batch_series(self._h, _ptr(t), k, _ptr(pp), _ptr(qq), m, c), "okpz_batch_series")
+        return [{s: (_moments_dict(m[i * n + s]), _corr_dict(c[i * n + s]) if with_autocorr else None)
+                 for s in self.members} for i in range(k)]
 
     def timing(self, enable: bool = True):
         _check(load().okpz_batch_timing(self._h, int(enable)), "okpz_batch_timing")

@@ -189,6 +189,89 @@ __global__ void batch_advance_kernel(uint64_t *mcs, const BatchSlot *slots, uint
 constexpr uint64_t kWaitSeconds = 20;  // far above any single tile's sweep
 constexpr uint32_t kStaticLds = 64;    // batch_kernel's static LDS, rounded up
 
+// ---------------------------------------------------------------- batched measurement
+// The measurement of every member in three launches: column-0 anchors (one
+// workgroup per member), band moments (one wave per band of any member, bands
+// numbered member-major through band_prefix) and the exact 128-bit totals
+// (one workgroup per member).  Same arithmetic as the single-lattice
+// measurement, only the band-to-lattice mapping differs.
+struct MeasureSlot {
+    const uint32_t *src;       // words measured
+    int32_t *h0;               // column-0 heights of src (written)
+    const uint32_t *snap;      // snapshot words (cross only)
+    const int32_t *h0s;        // column-0 heights of the snapshot
+    const uint32_t *copy_src;  // lattice words copied to the snapshot
+    uint32_t *copy_dst;        // snapshot buffer written by the copy kernel
+    uint64_t nwords;           // L^2 / 16
+    uint32_t L, nbx_log2;
+};
+
+__global__ void __launch_bounds__(1024) batch_anchors_kernel(const MeasureSlot *ms)
+{
+    __shared__ int32_t part[1024];
+    const MeasureSlot &m = ms[blockIdx.x];
+    anchors_body(m.src, m.L, m.nbx_log2, m.h0, part);
+}
+
+__device__ __forceinline__ uint32_t member_of(const uint32_t *prefix, uint32_t n, uint32_t i)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <bool CROSS>
+__global__ void __launch_bounds__(kMeasureThreads) batch_rows_kernel(const MeasureSlot *ms,
+                                                                     const uint32_t *band_prefix, uint32_t n,
+                                                                     int64_t *__restrict__ partial)
+{
+    __shared__ uint32_t lut[32];
+    __shared__ int32_t pair[CROSS ? 512 : 1];
+    build_tables<CROSS>(lut, pair);
+    __syncthreads();
+    const uint32_t gb = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
+    if (gb >= band_prefix[n]) return;
+    const uint32_t r = member_of(band_prefix, n, gb);
+    const MeasureSlot &m = ms[r];
+    rows_band<CROSS>(lut, pair, m.src, m.h0, m.snap, m.h0s, gb - band_prefix[r], m.nbx_log2,
+                     partial + static_cast<uint64_t>(gb) * kMomentFields);
+}
+
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const uint32_t *band_prefix,
+                                                           const int64_t *__restrict__ partial,
+                                                           int64_t *__restrict__ out)
+{
+    __shared__ uint64_t lo_s[kMomentFields][256];
+    __shared__ int64_t hi_s[kMomentFields][256];
+    const uint32_t r = blockIdx.x;
+    reduce_body(partial + static_cast<uint64_t>(band_prefix[r]) * kMomentFields, band_prefix[r + 1] - band_prefix[r],
+                out + 2 * kMomentFields * r, lo_s, hi_s);
+}
+
+// Snapshot copies: chunk c of the concatenated lattices (up to 16 KiB, one
+// workgroup of 256 lanes moving up to 4 x 16 B each; a lattice's last chunk
+// may be partial, L^2/16 words being a multiple of 4 for L >= 64).
+constexpr uint32_t kCopyChunkWords = 4096;
+
+__global__ void __launch_bounds__(256) batch_copy_kernel(const MeasureSlot *ms, const uint32_t *chunk_prefix,
+                                                         uint32_t n)
+{
+    const uint32_t c = blockIdx.x;
+    const uint32_t r = member_of(chunk_prefix, n, c);
+    const uint64_t base = static_cast<uint64_t>(c - chunk_prefix[r]) * kCopyChunkWords;
+    const uint4 *src = reinterpret_cast<const uint4 *>(ms[r].copy_src + base);
+    uint4 *dst = reinterpret_cast<uint4 *>(ms[r].copy_dst + base);
+    const uint64_t nvec = (ms[r].nwords - base) / 4;  // > 0: chunk c lies inside lattice r
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t i = threadIdx.x + 256u * k;
+        if (i < nvec) dst[i] = src[i];
+    }
+}
+
 }  // namespace
 
 struct okpz_batch {
@@ -223,6 +306,14 @@ struct okpz_batch {
     std::vector<TimedPair> pairs;
     uint64_t launches = 0;
     uint64_t attempts = 0;
+    // batched measurement: tables, per-band partials, totals (device and pinned)
+    MeasureSlot *d_meas = nullptr;
+    uint32_t *d_mprefix = nullptr;  // band prefix, then chunk prefix
+    int64_t *d_mpartial = nullptr;
+    int64_t *d_mout = nullptr;
+    uint8_t *h_mstage = nullptr;
+    int64_t *h_mout = nullptr;
+    size_t cap_meas = 0, cap_bands = 0;
 };
 
 namespace {
@@ -244,6 +335,12 @@ void batch_release(okpz_batch *b)
     (void)hipFree(b->d_error);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->h_error) (void)hipHostFree(b->h_error);
+    (void)hipFree(b->d_meas);
+    (void)hipFree(b->d_mprefix);
+    (void)hipFree(b->d_mpartial);
+    (void)hipFree(b->d_mout);
+    if (b->h_mstage) (void)hipHostFree(b->h_mstage);
+    if (b->h_mout) (void)hipHostFree(b->h_mout);
     delete b;
 }
 
@@ -729,6 +826,215 @@ int okpz_batch_get_timing(okpz_batch *b, double *ms, uint64_t *launches, uint64_
     if (ms) *ms = total;
     if (launches) *launches = b->launches;
     if (attempts) *attempts = b->attempts;
+    return OKPZ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int grow_measure(okpz_batch *b, size_t n, size_t bands)
+{
+    if (n > b->cap_meas) {
+        const size_t cap = std::max<size_t>(n, 2 * b->cap_meas);
+        (void)hipFree(b->d_meas);
+        (void)hipFree(b->d_mprefix);
+        (void)hipFree(b->d_mout);
+        if (b->h_mstage) (void)hipHostFree(b->h_mstage);
+        if (b->h_mout) (void)hipHostFree(b->h_mout);
+        b->d_meas = nullptr;
+        b->d_mprefix = nullptr;
+        b->d_mout = nullptr;
+        b->h_mstage = nullptr;
+        b->h_mout = nullptr;
+        b->cap_meas = 0;
+        if (hipMalloc(&b->d_meas, cap * sizeof(MeasureSlot)) != hipSuccess ||
+            hipMalloc(&b->d_mprefix, 2 * (cap + 1) * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&b->d_mout, cap * 2 * kMomentFields * sizeof(int64_t)) != hipSuccess ||
+            hipHostMalloc(&b->h_mstage, cap * sizeof(MeasureSlot) + 2 * (cap + 1) * sizeof(uint32_t),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&b->h_mout, cap * 2 * kMomentFields * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+            return OKPZ_ENOMEM;
+        b->cap_meas = cap;
+    }
+    if (bands > b->cap_bands) {
+        const size_t cap = std::max<size_t>(bands, 2 * b->cap_bands);
+        (void)hipFree(b->d_mpartial);
+        b->d_mpartial = nullptr;
+        b->cap_bands = 0;
+        if (hipMalloc(&b->d_mpartial, cap * kMomentFields * sizeof(int64_t)) != hipSuccess) return OKPZ_ENOMEM;
+        b->cap_bands = cap;
+    }
+    return OKPZ_OK;
+}
+
+// Measures every member (slot order) and leaves each member's 128-bit totals
+// in its host_out.  of_snapshot: copy the words to the snapshot first and
+// measure the snapshot (its anchors go to h0s); cross: also the sums against
+// the snapshot.  Synchronises the stream; a failed earlier batch launch is
+// reported as OKPZ_EWAIT.
+int batch_measure(okpz_batch *b, const std::vector<okpz_lattice *> &mem, bool of_snapshot, bool cross)
+{
+    const size_t n = mem.size();
+    if (n == 0) return OKPZ_OK;
+    if (n > 0xFFFFFFFFull / 2) return OKPZ_EINVAL;
+    std::vector<MeasureSlot> ms(n);
+    std::vector<uint32_t> bp(n + 1, 0), cp(n + 1, 0);
+    for (size_t i = 0; i < n; ++i) {
+        okpz_lattice *lat = mem[i];
+        const uint32_t L = lat->prm.L;
+        MeasureSlot &m = ms[i];
+        m.src = of_snapshot ? lat->snap : lat->words;
+        m.h0 = of_snapshot ? lat->h0s : lat->h0;
+        m.snap = cross ? lat->snap : nullptr;
+        m.h0s = cross ? lat->h0s : nullptr;
+        m.copy_src = of_snapshot ? lat->words : nullptr;
+        m.copy_dst = of_snapshot ? lat->snap : nullptr;
+        m.nwords = (uint64_t)L * L / 16;
+        m.L = L;
+        m.nbx_log2 = ilog2(L / 32);
+        const uint64_t bands = (uint64_t)bp[i] + L / 4;
+        const uint64_t chunks = (uint64_t)cp[i] + (m.nwords + kCopyChunkWords - 1) / kCopyChunkWords;
+        if (bands > 0xFFFFFFFFull || chunks > 0xFFFFFFFFull) return OKPZ_EINVAL;
+        bp[i + 1] = (uint32_t)bands;
+        cp[i + 1] = (uint32_t)chunks;
+    }
+    // the staging buffer and the tables may still be in use by a previous
+    // measurement only if it failed half-way: wait for the stream first
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int rc = grow_measure(b, n, bp[n]);
+    if (rc != OKPZ_OK) return rc;
+    MeasureSlot *hs = reinterpret_cast<MeasureSlot *>(b->h_mstage);
+    std::memcpy(hs, ms.data(), n * sizeof(MeasureSlot));
+    uint32_t *hp = reinterpret_cast<uint32_t *>(hs + n);
+    std::memcpy(hp, bp.data(), (n + 1) * sizeof(uint32_t));
+    std::memcpy(hp + n + 1, cp.data(), (n + 1) * sizeof(uint32_t));
+    HIP_TRY(hipMemcpyAsync(b->d_meas, hs, n * sizeof(MeasureSlot), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_mprefix, hp, 2 * (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
+    const uint32_t *d_bp = b->d_mprefix, *d_cp = b->d_mprefix + n + 1;
+    if (of_snapshot)
+        hipLaunchKernelGGL(batch_copy_kernel, dim3(cp[n]), dim3(256), 0, b->stream, b->d_meas, d_cp, (uint32_t)n);
+    hipLaunchKernelGGL(batch_anchors_kernel, dim3((uint32_t)n), dim3(1024), 0, b->stream, b->d_meas);
+    const uint32_t per_block = kMeasureThreads / 64;
+    const uint32_t blocks = (bp[n] + per_block - 1) / per_block;
+    if (cross)
+        hipLaunchKernelGGL((batch_rows_kernel<true>), dim3(blocks), dim3(kMeasureThreads), 0, b->stream, b->d_meas,
+                           d_bp, (uint32_t)n, b->d_mpartial);
+    else
+        hipLaunchKernelGGL((batch_rows_kernel<false>), dim3(blocks), dim3(kMeasureThreads), 0, b->stream, b->d_meas,
+                           d_bp, (uint32_t)n, b->d_mpartial);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3((uint32_t)n), dim3(256), 0, b->stream, d_bp, b->d_mpartial,
+                       b->d_mout);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(b->h_mout, b->d_mout, n * 2 * kMomentFields * sizeof(int64_t), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->h_error, b->d_error, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (*b->h_error) b->failed = true;
+    if (b->failed) return OKPZ_EWAIT;
+    for (size_t i = 0; i < n; ++i)
+        std::memcpy(mem[i]->host_out, b->h_mout + 2 * kMomentFields * i, 2 * kMomentFields * sizeof(int64_t));
+    return OKPZ_OK;
+}
+
+std::vector<okpz_lattice *> members_of(const okpz_batch *b)
+{
+    std::vector<okpz_lattice *> mem;
+    for (okpz_lattice *m : b->slots)
+        if (m) mem.push_back(m);
+    return mem;
+}
+
+int batch_snapshot(okpz_batch *b)
+{
+    const std::vector<okpz_lattice *> mem = members_of(b);
+    for (okpz_lattice *lat : mem) {
+        const uint32_t L = lat->prm.L;
+        if (!lat->snap && hipMalloc(&lat->snap, (size_t)L * L / 4) != hipSuccess) {
+            lat->snap = nullptr;
+            return OKPZ_ENOMEM;
+        }
+        if (!lat->h0s && hipMalloc(&lat->h0s, L * sizeof(int32_t)) != hipSuccess) {
+            lat->h0s = nullptr;
+            return OKPZ_ENOMEM;
+        }
+        lat->has_snap = false;
+    }
+    const int rc = batch_measure(b, mem, true, false);
+    if (rc != OKPZ_OK) return rc;
+    for (okpz_lattice *lat : mem) {
+        lat->snap_s1 = pair_to_i128(lat->host_out + 0) + pair_to_i128(lat->host_out + 2);
+        lat->snap_mcs = lat->mcs;
+        lat->has_snap = true;
+    }
+    return OKPZ_OK;
+}
+
+int batch_observe(okpz_batch *b, okpz_moments *moments, okpz_correlation *corr)
+{
+    const std::vector<okpz_lattice *> mem = members_of(b);
+    if (corr)
+        for (okpz_lattice *lat : mem)
+            if (!lat->has_snap) return OKPZ_ESTATE;
+    const int rc = batch_measure(b, mem, false, corr != nullptr);
+    if (rc != OKPZ_OK) return rc;
+    for (size_t s = 0; s < b->slots.size(); ++s) {
+        okpz_lattice *lat = b->slots[s];
+        if (!lat) {
+            std::memset(&moments[s], 0, sizeof(okpz_moments));
+            if (corr) std::memset(&corr[s], 0, sizeof(okpz_correlation));
+            continue;
+        }
+        fill_moments(lat, &moments[s]);
+        if (corr) fill_correlation(lat, &corr[s]);
+    }
+    return OKPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int okpz_batch_snapshot(okpz_batch *b)
+{
+    if (!b) return OKPZ_EINVAL;
+    if (b->failed) return OKPZ_EWAIT;
+    return batch_snapshot(b);
+}
+
+int okpz_batch_observe(okpz_batch *b, okpz_moments *moments, okpz_correlation *corr)
+{
+    if (!b || !moments) return OKPZ_EINVAL;
+    if (b->failed) return OKPZ_EWAIT;
+    return batch_observe(b, moments, corr);
+}
+
+int okpz_batch_series(okpz_batch *b, const uint64_t *times, size_t n_times, const double *p, const double *q,
+                      okpz_moments *moments, okpz_correlation *corr)
+{
+    if (!b || (n_times > 0 && (!times || !moments)) || !p || !q) return OKPZ_EINVAL;
+    if (b->failed) return OKPZ_EWAIT;
+    const size_t ns = b->slots.size();
+    for (size_t i = 1; i < n_times; ++i)
+        if (times[i] < times[i - 1]) return OKPZ_EINVAL;
+    if (n_times > 0 && times[n_times - 1] > kMcsLimit) return OKPZ_EOVERFLOW;
+    for (size_t s = 0; s < ns; ++s) {
+        okpz_lattice *lat = b->slots[s];
+        if (!lat) continue;
+        if (!(p[s] >= 0.0 && p[s] <= 1.0 && q[s] >= 0.0 && q[s] <= 1.0)) return OKPZ_EINVAL;
+        if (n_times > 0 && lat->mcs + times[n_times - 1] > kMcsLimit) return OKPZ_EOVERFLOW;
+        if (corr && !lat->has_snap) return OKPZ_ESTATE;
+    }
+    std::vector<uint64_t> step(ns);
+    uint64_t t = 0;
+    for (size_t i = 0; i < n_times; ++i) {
+        for (size_t s = 0; s < ns; ++s) step[s] = b->slots[s] ? times[i] - t : 0;
+        t = times[i];
+        int rc = okpz_batch_run(b, step.data(), p, q);
+        if (rc != OKPZ_OK) return rc;
+        rc = batch_observe(b, moments + i * ns, corr ? corr + i * ns : nullptr);
+        if (rc != OKPZ_OK) return rc;
+    }
     return OKPZ_OK;
 }
 

@@ -282,4 +282,9 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
     return a;
 }
 
+// Moments (and correlation, against the snapshot) from the 128-bit totals in
+// lat->host_out.
+void fill_moments(const okpz_lattice *lat, okpz_moments *out);
+void fill_correlation(const okpz_lattice *lat, okpz_correlation *out);
+
 }  // namespace okpz_host

@@ -849,10 +849,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs A)
 
 // Column-0 anchors h(0,y): one workgroup; each thread owns a run of bands,
 // reads the sy words of block 0 of each band, and a block scan joins the runs.
-static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
-                                                       uint32_t nbx_log2, int32_t *__restrict__ h0)
+__device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words, uint32_t L, uint32_t nbx_log2,
+                                             int32_t *__restrict__ h0, int32_t *part)
 {
-    __shared__ int32_t part[1024];
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     const uint32_t nband = L >> 2;
     const uint32_t chunk = (nband + T - 1) / T;
@@ -886,6 +885,13 @@ static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__
             h0[y] = h;
         }
     }
+}
+
+static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
+                                                       uint32_t nbx_log2, int32_t *__restrict__ h0)
+{
+    __shared__ int32_t part[1024];
+    anchors_body(words, L, nbx_log2, h0, part);
 }
 
 __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t v, int32_t &total)
@@ -955,20 +961,14 @@ constexpr int kMeasureThreads = 256;
 // sum q^2.  With a snapshot (CROSS), sum h_t h_s is accumulated the same way,
 // and the slope overlap (slope variables that are 1 in both states, for the
 // slope autocorrelation C_s) is a population count of the ANDed words.
+// One wave: the moments of band `band` of one lattice into out[0..5].
 template <bool CROSS>
-__global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *__restrict__ words,
-                                                               const int32_t *__restrict__ h0,
-                                                               const uint32_t *__restrict__ snap,
-                                                               const int32_t *__restrict__ h0s, uint32_t L,
-                                                               uint32_t nbx_log2, int64_t *__restrict__ partial)
+__device__ __forceinline__ void rows_band(const uint32_t *lut, const int32_t *pair, const uint32_t *__restrict__ words,
+                                          const int32_t *__restrict__ h0, const uint32_t *__restrict__ snap,
+                                          const int32_t *__restrict__ h0s, uint32_t band, uint32_t nbx_log2,
+                                          int64_t *__restrict__ out)
 {
-    __shared__ uint32_t lut[32];
-    __shared__ int32_t pair[CROSS ? 512 : 1];
-    build_tables<CROSS>(lut, pair);
-    __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t band = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
-    if (band >= (L >> 2)) return;
     const uint32_t nbx = 1u << nbx_log2;
     const uint64_t band_base = (static_cast<uint64_t>(band) << nbx_log2) << 3;
     int32_t carry[4] = {0, 0, 0, 0}, carry_s[4] = {0, 0, 0, 0};
@@ -1052,7 +1052,6 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
         ov = wave_sum_i64((int64_t)overlap);
     }
     if (lane == 0) {
-        int64_t *out = partial + static_cast<uint64_t>(band) * kMomentFields;
         out[0] = s1e;
         out[1] = s1o;
         out[2] = s2e;
@@ -1060,6 +1059,23 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
         out[4] = sts;
         out[5] = ov;
     }
+}
+
+template <bool CROSS>
+__global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *__restrict__ words,
+                                                               const int32_t *__restrict__ h0,
+                                                               const uint32_t *__restrict__ snap,
+                                                               const int32_t *__restrict__ h0s, uint32_t L,
+                                                               uint32_t nbx_log2, int64_t *__restrict__ partial)
+{
+    __shared__ uint32_t lut[32];
+    __shared__ int32_t pair[CROSS ? 512 : 1];
+    build_tables<CROSS>(lut, pair);
+    __syncthreads();
+    const uint32_t band = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
+    if (band >= (L >> 2)) return;
+    rows_band<CROSS>(lut, pair, words, h0, snap, h0s, band, nbx_log2,
+                     partial + static_cast<uint64_t>(band) * kMomentFields);
 }
 
 // 128-bit signed accumulate (two's complement in (lo, hi)).
@@ -1071,11 +1087,10 @@ __device__ __forceinline__ void add_i128(uint64_t &lo, int64_t &hi, uint64_t blo
 }
 
 // Final exact reduction of the per-row partials into 128-bit totals.
-static __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__restrict__ partial, uint32_t nrows,
-                                                     int64_t *__restrict__ out)
+// One workgroup of 256 lanes: 128-bit totals of nrows rows of partials.
+__device__ __forceinline__ void reduce_body(const int64_t *__restrict__ partial, uint32_t nrows,
+                                            int64_t *__restrict__ out, uint64_t (*lo_s)[256], int64_t (*hi_s)[256])
 {
-    __shared__ uint64_t lo_s[kMomentFields][256];
-    __shared__ int64_t hi_s[kMomentFields][256];
     const uint32_t tid = threadIdx.x;
     for (int f = 0; f < kMomentFields; ++f) {
         uint64_t lo = 0;
@@ -1103,6 +1118,14 @@ static __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__res
         out[2 * tid] = static_cast<int64_t>(lo_s[tid][0]);
         out[2 * tid + 1] = hi_s[tid][0];
     }
+}
+
+static __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__restrict__ partial, uint32_t nrows,
+                                                     int64_t *__restrict__ out)
+{
+    __shared__ uint64_t lo_s[kMomentFields][256];
+    __shared__ int64_t hi_s[kMomentFields][256];
+    reduce_body(partial, nrows, out, lo_s, hi_s);
 }
 
 }  // namespace okpz

@@ -6,6 +6,7 @@
 // device-wide synchronisation between sets (Sec. 3.1).
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdio>
 #include <new>
 
@@ -140,7 +141,9 @@ int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_
     return OKPZ_OK;
 }
 
-void fill_moments(const okpz_lattice *lat, okpz_moments *out)
+}  // namespace
+
+void okpz_host::fill_moments(const okpz_lattice *lat, okpz_moments *out)
 {
     const uint64_t L = lat->prm.L;
     const int64_t *r = lat->host_out;
@@ -161,7 +164,7 @@ void fill_moments(const okpz_lattice *lat, okpz_moments *out)
     out->w2_sub = std::ldexp(i128_to_double(2 * ((ne * s2e - s1e * s1e) + (no * s2o - s1o * s1o))), -sh);
 }
 
-void fill_correlation(const okpz_lattice *lat, okpz_correlation *out);
+namespace {
 
 // host packing / unpacking: site (x, y) lives in block (x/32, y/4), word
 // 8 * block + y%4 (sx) or 8 * block + 4 + y%4 (sy), bit x%32
@@ -483,9 +486,7 @@ int okpz_autocorr(okpz_lattice *lat, okpz_correlation *out)
 
 }  // extern "C"
 
-namespace {
-
-void fill_correlation(const okpz_lattice *lat, okpz_correlation *out)
+void okpz_host::fill_correlation(const okpz_lattice *lat, okpz_correlation *out)
 {
     const uint64_t L = lat->prm.L;
     const __int128 n = (__int128)L * L;
@@ -502,8 +503,6 @@ void fill_correlation(const okpz_lattice *lat, okpz_correlation *out)
     out->overlap = (int64_t)ov;
     out->c_s = std::ldexp(i128_to_double(2 * ov - n), -2 - 2 * (int)ilog2(L));
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -580,6 +579,157 @@ int okpz_get_words(okpz_lattice *lat, uint32_t *words)
 {
     if (!lat || !words) return OKPZ_EINVAL;
     HIP_TRY(hipMemcpyAsync(words, lat->words, lat->nwords * sizeof(uint32_t), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return OKPZ_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+// Blob: a 128-byte header (magic, version, flags, parameters, MCS counts,
+// word count, checksum) followed by the lattice words and, if the snapshot
+// is saved, the snapshot words, all in the device layout.
+
+}  // extern "C"
+
+namespace {
+
+constexpr char kCkpMagic[8] = {'O', 'K', 'P', 'Z', 'C', 'K', 'P', 0};
+constexpr uint32_t kCkpVersion = 1;
+constexpr size_t kCkpHeader = 128;
+
+struct CkpHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t flags;  // bit 0: snapshot words follow the lattice words
+    okpz_params prm;
+    uint64_t mcs, snap_mcs, nwords;
+    uint64_t checksum;  // over the header (this field zero) and the payload
+};
+static_assert(sizeof(CkpHeader) <= kCkpHeader, "checkpoint header");
+
+// Multiply-xor checksum over 8-byte units (n a multiple of 8).
+uint64_t ckp_mix(uint64_t h, const uint8_t *p, size_t n)
+{
+    for (size_t i = 0; i < n; i += 8) {
+        uint64_t v;
+        std::memcpy(&v, p + i, 8);
+        h = (h ^ v) * 0x100000001B3ull;
+        h ^= h >> 29;
+    }
+    return h;
+}
+
+size_t ckp_bytes(const okpz_lattice *lat, bool snap)
+{
+    return kCkpHeader + (snap ? 2 : 1) * lat->nwords * sizeof(uint32_t);
+}
+
+// Word-level check of a height state (as valid_surface, on the packed words):
+// every plaquette closes, sx(x, y-1) + sy(x, y) = sy(x-1, y) + sx(x, y), and
+// the slopes of row 0 and of column 0 sum to zero.  On the torus a closed
+// slope field has the same sum along every row (every column), so these two
+// loops suffice.
+bool valid_words(const uint32_t *w, uint32_t L)
+{
+    const uint32_t nbx = L / 32, nrow = L;
+    auto sx = [&](uint32_t bx, uint32_t y) { return w[(((uint64_t)(y >> 2) * nbx + bx) << 3) + (y & 3)]; };
+    auto sy = [&](uint32_t bx, uint32_t y) { return w[(((uint64_t)(y >> 2) * nbx + bx) << 3) + 4 + (y & 3)]; };
+    for (uint32_t y = 0; y < nrow; ++y) {
+        const uint32_t ym = (y + L - 1) & (L - 1);
+        for (uint32_t bx = 0; bx < nbx; ++bx) {
+            const uint32_t a = sx(bx, ym), b = sy(bx, y), d = sx(bx, y);
+            const uint32_t prev = sy((bx + nbx - 1) % nbx, y);
+            const uint32_t c = (b << 1) | (prev >> 31);  // sy(x-1, y) at bit x
+            if ((a ^ b) != (c ^ d) || (a & b) != (c & d)) return false;
+        }
+    }
+    uint64_t row0 = 0, col0 = 0;
+    for (uint32_t bx = 0; bx < nbx; ++bx) row0 += (uint64_t)__builtin_popcount(sx(bx, 0));
+    for (uint32_t y = 0; y < nrow; ++y) col0 += sy(0, y) & 1u;
+    return 2 * row0 == L && 2 * col0 == L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int okpz_checkpoint_size(const okpz_lattice *lat, int with_snapshot, size_t *nbytes)
+{
+    if (!lat || !nbytes) return OKPZ_EINVAL;
+    if (with_snapshot && !lat->has_snap) return OKPZ_ESTATE;
+    *nbytes = ckp_bytes(lat, with_snapshot != 0);
+    return OKPZ_OK;
+}
+
+int okpz_save(okpz_lattice *lat, int with_snapshot, void *host_buf, size_t nbytes)
+{
+    if (!lat || !host_buf) return OKPZ_EINVAL;
+    const bool snap = with_snapshot != 0;
+    if (snap && !lat->has_snap) return OKPZ_ESTATE;
+    if (nbytes < ckp_bytes(lat, snap)) return OKPZ_EINVAL;
+    uint8_t *out = static_cast<uint8_t *>(host_buf);
+    const size_t wb = lat->nwords * sizeof(uint32_t);
+    HIP_TRY(hipMemcpyAsync(out + kCkpHeader, lat->words, wb, hipMemcpyDeviceToHost, lat->stream));
+    if (snap) HIP_TRY(hipMemcpyAsync(out + kCkpHeader + wb, lat->snap, wb, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    CkpHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kCkpMagic, sizeof(h.magic));
+    h.version = kCkpVersion;
+    h.flags = snap ? 1u : 0u;
+    h.prm = lat->prm;
+    h.mcs = lat->mcs;
+    h.snap_mcs = snap ? lat->snap_mcs : 0;
+    h.nwords = lat->nwords;
+    std::memset(out, 0, kCkpHeader);
+    std::memcpy(out, &h, sizeof(h));
+    h.checksum = ckp_mix(ckp_mix(0xCBF29CE484222325ull, out, kCkpHeader), out + kCkpHeader, (snap ? 2 : 1) * wb);
+    std::memcpy(out, &h, sizeof(h));
+    return OKPZ_OK;
+}
+
+int okpz_load(okpz_lattice *lat, const void *host_buf, size_t nbytes)
+{
+    if (!lat || !host_buf || nbytes < kCkpHeader) return OKPZ_EINVAL;
+    const uint8_t *in = static_cast<const uint8_t *>(host_buf);
+    CkpHeader h;
+    std::memcpy(&h, in, sizeof(h));
+    if (std::memcmp(h.magic, kCkpMagic, sizeof(h.magic)) != 0 || h.version != kCkpVersion || (h.flags & ~1u))
+        return OKPZ_EINVAL;
+    if (std::memcmp(&h.prm, &lat->prm, sizeof(okpz_params)) != 0 || h.nwords != lat->nwords) return OKPZ_EINVAL;
+    const bool snap = (h.flags & 1u) != 0;
+    if (h.mcs >= kMcsLimit || (snap && h.snap_mcs > h.mcs)) return OKPZ_EINVAL;
+    const size_t wb = lat->nwords * sizeof(uint32_t);
+    if (nbytes < ckp_bytes(lat, snap)) return OKPZ_EINVAL;
+    std::vector<uint8_t> head(in, in + kCkpHeader);
+    std::memset(head.data() + offsetof(CkpHeader, checksum), 0, sizeof(uint64_t));
+    if (ckp_mix(ckp_mix(0xCBF29CE484222325ull, head.data(), kCkpHeader), in + kCkpHeader, (snap ? 2 : 1) * wb) !=
+        h.checksum)
+        return OKPZ_EINVAL;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(in + kCkpHeader);
+    if (!valid_words(words, lat->prm.L) || (snap && !valid_words(words + lat->nwords, lat->prm.L)))
+        return OKPZ_EINVAL;
+    if (snap && !lat->snap) {
+        const uint32_t L = lat->prm.L;
+        if (hipMalloc(&lat->snap, (size_t)L * L / 4) != hipSuccess) {
+            lat->snap = nullptr;
+            return OKPZ_ENOMEM;
+        }
+    }
+    if (snap && !lat->h0s && hipMalloc(&lat->h0s, lat->prm.L * sizeof(int32_t)) != hipSuccess) {
+        lat->h0s = nullptr;
+        return OKPZ_ENOMEM;
+    }
+    HIP_TRY(hipMemcpyAsync(lat->words, words, wb, hipMemcpyHostToDevice, lat->stream));
+    lat->mcs = h.mcs;
+    lat->has_snap = false;
+    if (snap) {
+        HIP_TRY(hipMemcpyAsync(lat->snap, words + lat->nwords, wb, hipMemcpyHostToDevice, lat->stream));
+        const int rc = run_measure(lat, false, lat->snap, lat->h0s);
+        if (rc != OKPZ_OK) return rc;
+        lat->snap_s1 = pair_to_i128(lat->host_out + 0) + pair_to_i128(lat->host_out + 2);
+        lat->snap_mcs = h.snap_mcs;
+        lat->has_snap = true;
+    }
     HIP_TRY(hipStreamSynchronize(lat->stream));
     return OKPZ_OK;
 }

@@ -26,13 +26,10 @@ def gpu_series(okpz, L, D, C, scheme, p, q, n, times, seed):
     b = okpz.Batch()
     lats = [b.lattice(L, D, D, C, C, scheme, seed=seed, stream=r) for r in range(n)]
     out = np.zeros((n, len(times)))
-    t = 0
-    for i, tt in enumerate(times):
-        b.run([tt - t] * n, p, q)
-        b.sync()
-        t = tt
-        for r, lat in enumerate(lats):
-            out[r, i] = lat.measure()["w2"]
+    series = b.series(times, p, q)
+    for i, obs in enumerate(series):
+        for r in range(n):
+            out[r, i] = obs[r][0]["w2"]
     b.close()
     for lat in lats:
         lat.close()
