@@ -228,15 +228,14 @@ __global__ void __launch_bounds__(kMeasureThreads) batch_rows_kernel(const Measu
                                                                      const uint32_t *band_prefix, uint32_t n,
                                                                      int64_t *__restrict__ partial)
 {
-    __shared__ uint32_t lut[32];
-    __shared__ int32_t pair[CROSS ? 512 : 1];
-    build_tables<CROSS>(lut, pair);
+    __shared__ __align__(8) uint32_t lut[512];
+    build_tables(lut);
     __syncthreads();
     const uint32_t gb = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
     if (gb >= band_prefix[n]) return;
     const uint32_t r = member_of(band_prefix, n, gb);
     const MeasureSlot &m = ms[r];
-    rows_band<CROSS>(lut, pair, m.src, m.h0, m.snap, m.h0s, gb - band_prefix[r], m.nbx_log2,
+    rows_band<CROSS>(lut, m.src, m.h0, m.snap, m.h0s, gb - band_prefix[r], m.nbx_log2,
                      partial + static_cast<uint64_t>(gb) * kMomentFields);
 }
 

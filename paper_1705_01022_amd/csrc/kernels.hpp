@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "philox.hpp"
 
 namespace okpz {
@@ -641,6 +643,14 @@ __device__ __forceinline__ void db_columns_round(const StepArgs &A, uint32_t *ld
     // only there; a site one past the domain edge is never a neighbour's), so
     // the rim needs no separate test; it is worked out only for deferred
     // attempts (a corner goes after the edges).
+    //
+    // The first pass takes a lane's cells bottom to top, so the attempt of the
+    // cell below in the same lane has already run when mine runs: that
+    // dependency needs no deferral, unless the attempt below is itself
+    // deferred (it then sits on its cell's right column, so mine is a corner
+    // and goes after it).  The dependency on the cell to the right (another
+    // lane, same instruction) and on the cell below the lane's bottom cell
+    // (another lane) always defers.
     const uint32_t cxm = (1u << A.log2Cx) - 1u, cym = (1u << A.log2Cy) - 1u;
     const uint32_t shx = (f16 >> 2) & cxm, shy = (f16 >> 8) & cym;  // this round's cell-grid shift
     auto bottom_row = [&](int j) { return (((d[j].pos >> 16) - shy - base_v[j]) & (A.Dy - 1u)) == cym; };
@@ -651,16 +661,17 @@ __device__ __forceinline__ void db_columns_round(const StepArgs &A, uint32_t *ld
     bool def[CPT], remote[CPT];
     bool any = false;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
+    for (int j = CPT - 1; j >= 0; --j) {
         const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)d[j].pos);
         const uint32_t pd = j + 1 < CPT ? d[j + 1 < CPT ? j + 1 : j].pos : pbot;
-        def[j] = pr == d[j].pos + 1u || pd == d[j].pos + 0x10000u;
+        const bool below = pd == d[j].pos + 0x10000u && (j == CPT - 1 || def[j + 1 < CPT ? j + 1 : j]);
+        def[j] = pr == d[j].pos + 1u || below;
         // remote: a bottom-row attempt of a bottom cell whose column below is in another wave
         remote[j] = j == CPT - 1 && border && def[j] && bottom_row(j);
         any |= remote[j];
     }
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) attempt(lds, d[j], !def[j]);
+    for (int j = CPT - 1; j >= 0; --j) attempt(lds, d[j], !def[j]);
     wave_order();
     bool cor[CPT];
 #pragma unroll
@@ -894,16 +905,20 @@ static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__
     anchors_body(words, L, nbx_log2, h0, part);
 }
 
+// Exclusive prefix sum over the 64 lanes of a wave and the wave's total, by
+// data-parallel-primitive moves: shifts by 1, 2, 4, 8 within rows of 16
+// lanes (lanes shifted in from outside the row read 0), then the last lane of
+// row 0 into rows 1 and 3 and the last lane of row 1 into rows 2 and 3.
 __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t v, int32_t &total)
 {
-    const uint32_t lane = threadIdx.x & 63u;
     int32_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int32_t o = __shfl_up(inc, off, 64);
-        if (lane >= (uint32_t)off) inc += o;
-    }
-    total = __shfl(inc, 63, 64);
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xF, 0xF, true);  // row_shr:1
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xF, 0xF, true);  // row_shr:2
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xF, 0xF, true);  // row_shr:4
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xF, 0xF, true);  // row_shr:8
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    total = __builtin_amdgcn_readlane(inc, 63);
     return inc - v;
 }
 
@@ -916,54 +931,89 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
 
 constexpr int kMomentFields = 6;  // S1_even, S1_odd, S2_even, S2_odd, S_ts, slope overlap
 
-// Row-nibble table: for 4 consecutive sites of a row (x % 4 = 0..3) with
-// steps e_i = 2 b_i - 1 (e_0 = 0 for the row's first site, entries 16..31)
-// and prefixes p_i = e_0 + .. + e_i: bits 0-7 p0+p2, 8-15 p1+p3 (signed),
-// 16-20 p0^2+p2^2, 21-25 p1^2+p3^2, 26-29 p3+4.  Pair table: sum_i pt_i ps_i
-// for two nibbles of the same sites (index first*256 + nt*16 + ns).
-__device__ __forceinline__ void row_prefixes(uint32_t nib, uint32_t first, int32_t (&p)[4])
+// Spread-prefix table of a byte b (8 sites, bit m = slope bit of site m),
+// two words per entry: byte m of word j = number of 1 bits among bits
+// 0 .. 4j + m.
+__device__ void build_tables(uint32_t *lut)
 {
-    int32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (!(i == 0 && first)) acc += 2 * (int32_t)((nib >> i) & 1u) - 1;
-        p[i] = acc;
-    }
-}
-
-template <bool CROSS>
-__device__ void build_tables(uint32_t *lut, int32_t *pair)
-{
-    for (uint32_t i = threadIdx.x; i < 32; i += blockDim.x) {
-        int32_t p[4];
-        row_prefixes(i & 15u, i >> 4, p);
-        lut[i] = (uint32_t)(uint8_t)(int8_t)(p[0] + p[2]) | ((uint32_t)(uint8_t)(int8_t)(p[1] + p[3]) << 8) |
-                 ((uint32_t)(p[0] * p[0] + p[2] * p[2]) << 16) | ((uint32_t)(p[1] * p[1] + p[3] * p[3]) << 21) |
-                 ((uint32_t)(p[3] + 4) << 26);
-    }
-    if (CROSS)
-        for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) {
-            int32_t pt[4], ps[4];
-            row_prefixes((i >> 4) & 15u, i >> 8, pt);
-            row_prefixes(i & 15u, i >> 8, ps);
-            pair[i] = pt[0] * ps[0] + pt[1] * ps[1] + pt[2] * ps[2] + pt[3] * ps[3];
+    for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) {
+        uint32_t acc = 0, e[2] = {0u, 0u};
+        for (uint32_t m = 0; m < 8; ++m) {
+            acc += (b >> m) & 1u;
+            e[m >> 2] |= acc << (8 * (m & 3));
         }
+        lut[2 * b] = e[0];
+        lut[2 * b + 1] = e[1];
+    }
 }
 
 constexpr int kMeasureThreads = 256;
 
-// Per-band partial moments.  One wave per band (4 site rows); lane l handles
-// block l of each chunk of 64 blocks (32 sites of each of the 4 rows).
-// Within its block a lane accumulates sums of heights relative to the
-// block's start, a wave scan gives the block offsets, and the relative sums
-// are shifted to absolute heights: with A the height before the block and q
-// the relative heights, sum h = n A + sum q and sum h^2 = n A^2 + 2 A sum q +
-// sum q^2.  With a snapshot (CROSS), sum h_t h_s is accumulated the same way,
-// and the slope overlap (slope variables that are 1 in both states, for the
-// slope autocorrelation C_s) is a population count of the ANDed words.
-// One wave: the moments of band `band` of one lattice into out[0..5].
+// One row of one 32-site block, bit i = slope bit of site x0 + i (x0 a
+// multiple of 32).  Relative heights q_i = sum_{j <= i} (2 b_j - 1) (for the
+// lattice's first block site 0 has no step: b_0 is cleared and q_i =
+// sum_{1 <= j <= i} (2 b_j - 1)) are formed four at a time as offset bytes
+// u_i = q_i + 64 in [32, 96]: u = 2 P + (63 - i) (+1 in the first block) with
+// P_i the number of 1 bits among bits 0 .. i, from the byte's spread-prefix
+// table entry plus the count of the bytes before (broadcast to every byte).
+// Byte dot products then give sums of u and u^2 over all sites and over the
+// sites of one parity class (the class bytes of two nibbles gathered into
+// one word).  Returns q_31, the block's height change; U[k] keeps the bytes of
+// nibble k for a cross product.  MOM = false: only the sum of u over all
+// sites (what a snapshot row needs).  FIRST: the chunk holding the lattice's
+// first block, in lane 0 (the only lane that takes the first-block path).
+template <int R, bool MOM, bool FIRST>
+__device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, uint32_t (&U)[8], uint32_t &u2,
+                                               uint32_t &u2e, uint32_t &su, uint32_t &sue)
+{
+    const bool f = FIRST && (threadIdx.x & 63u) == 0u;
+    const uint32_t dl = f ? 0x01010101u : 0u;
+    // parity class "even" (x + y even): even i on even rows, odd i on odd rows;
+    // bytes (m, m + 2) of nibbles k and k + 1 (permute selectors: 0-3 pick bytes
+    // of the second operand, 4-7 of the first)
+    constexpr uint32_t sel = (R & 1) ? 0x07050301u : 0x06040200u;
+    if (f) w &= ~1u;
+    uint32_t B = 0u, s2 = 0u, s2e = 0u, s1 = 0u, s1e = 0u;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint32_t off = ((w >> (8 * m)) & 0xFFu) << 3;  // byte offset of the table entry
+        const uint2 e = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lut) + off);
+        const uint32_t pb0 = e.x + B, pb1 = e.y + B;
+        B = __builtin_amdgcn_perm(pb1, pb1, 0x07070707u);  // P_{8m+7} in every byte
+        const uint32_t c0 = (63u - 8u * (uint32_t)m) * 0x01010101u - 0x03020100u + dl;  // bytes 63 - i
+        const uint32_t u0 = (pb0 << 1) + c0, u1 = (pb1 << 1) + (c0 - 0x04040404u);
+        U[2 * m] = u0;
+        U[2 * m + 1] = u1;
+        s1 = __builtin_amdgcn_udot4(u0, 0x01010101u, s1, false);
+        s1 = __builtin_amdgcn_udot4(u1, 0x01010101u, s1, false);
+        if (MOM) {
+            s2 = __builtin_amdgcn_udot4(u0, u0, s2, false);
+            s2 = __builtin_amdgcn_udot4(u1, u1, s2, false);
+            const uint32_t ev = __builtin_amdgcn_perm(u1, u0, sel);
+            s2e = __builtin_amdgcn_udot4(ev, ev, s2e, false);
+            s1e = __builtin_amdgcn_udot4(ev, 0x01010101u, s1e, false);
+        }
+    }
+    u2 += s2;
+    u2e += s2e;
+    su = s1;
+    sue = s1e;
+    return 2 * (int32_t)(B & 0xFFu) - 32 + (f ? 1 : 0);
+}
+
+// One wave: the moments of band `band` of one lattice into out[0..5].  Lane l
+// handles block l of each chunk of 64 blocks (32 sites of each of the band's
+// 4 rows); a wave scan of the blocks' height changes gives each block's
+// starting height A.  With q the relative heights of a block row (16 sites
+// per parity class), sum h = 16 A + sum q and sum h^2 = 2 A (8 A + sum q) +
+// sum q^2 per class; the A-dependent parts are accumulated per row in 64 bits,
+// the sums of u and u^2 (A-independent) in 32 bits and turned into sums of q
+// and q^2 at the end (q = u - 64).  With a snapshot (CROSS), sum h_t h_s =
+// A_t (32 A_s + sum q_s) + A_s sum q_t + sum q_t q_s over the block row, and
+// the slope overlap (slope variables that are 1 in both states, for the slope
+// autocorrelation C_s) is a population count of the ANDed words.
 template <bool CROSS>
-__device__ __forceinline__ void rows_band(const uint32_t *lut, const int32_t *pair, const uint32_t *__restrict__ words,
+__device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *__restrict__ words,
                                           const int32_t *__restrict__ h0, const uint32_t *__restrict__ snap,
                                           const int32_t *__restrict__ h0s, uint32_t band, uint32_t nbx_log2,
                                           int64_t *__restrict__ out)
@@ -972,9 +1022,20 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const int32_t *pa
     const uint32_t nbx = 1u << nbx_log2;
     const uint64_t band_base = (static_cast<uint64_t>(band) << nbx_log2) << 3;
     int32_t carry[4] = {0, 0, 0, 0}, carry_s[4] = {0, 0, 0, 0};
-    int64_t s1e = 0, s1o = 0, s2e = 0, s2o = 0, sts = 0;
-    uint32_t overlap = 0;  // at most 8 L per band
-    for (uint32_t base = 0; base < nbx; base += 64) {
+    int32_t h0r[4], h0sr[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        h0r[r] = h0[4 * band + r];
+        if (CROSS) h0sr[r] = h0s[4 * band + r];
+    }
+    int64_t lin_e = 0, lin_o = 0, quad_e = 0, quad_o = 0, xa = 0;
+    uint32_t u2 = 0, u2e = 0, ue = 0, uall = 0, us_all = 0, uts = 0;
+    uint32_t rows = 0;      // block rows this lane took part in
+    uint32_t overlap = 0;   // at most 8 L per band
+    // one chunk of 64 blocks; FIRST: the band's first chunk, whose lane 0
+    // holds the lattice's first block (site 0 without a step)
+    auto chunk = [&](uint32_t base, auto first_c) {
+        constexpr bool FIRST = decltype(first_c)::value;
         const uint32_t bx = base + lane;
         const bool active = bx < nbx;
         uint4 wv = make_uint4(0, 0, 0, 0), sv = make_uint4(0, 0, 0, 0);
@@ -990,58 +1051,61 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const int32_t *pa
         }
         const uint32_t wk[4] = {wv.x, wv.y, wv.z, wv.w};
         const uint32_t sk[4] = {sv.x, sv.y, sv.z, sv.w};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            // relative sums over the lane's 32 sites of row y = 4 band + r
-            int32_t R = 0, rel1e = 0, rel1o = 0, rel2e = 0, rel2o = 0;
-            int32_t Rs = 0, rel1s = 0, xrel = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t first = (bx == 0u && k == 0) ? 16u : 0u;
-                const uint32_t nib = (wk[r] >> (4 * k)) & 0xFu;
-                const uint32_t e = lut[first + nib];
-                const int32_t s02 = (int32_t)(int8_t)(e & 0xFFu), s13 = (int32_t)(int8_t)((e >> 8) & 0xFFu);
-                const int32_t q02 = (int32_t)((e >> 16) & 31u), q13 = (int32_t)((e >> 21) & 31u);
-                const int32_t T = (int32_t)((e >> 26) & 15u) - 4;
-                // even rows: sites x%4 = 0,2 are the even class (x+y even); odd rows: 1,3
-                const int32_t sE = (r & 1) ? s13 : s02, sO = (r & 1) ? s02 : s13;
-                const int32_t qE = (r & 1) ? q13 : q02, qO = (r & 1) ? q02 : q13;
-                rel1e += 2 * R + sE;
-                rel1o += 2 * R + sO;
-                rel2e += 2 * R * R + 2 * R * sE + qE;
-                rel2o += 2 * R * R + 2 * R * sO + qO;
-                if (CROSS) {
-                    const uint32_t nibs = (sk[r] >> (4 * k)) & 0xFu;
-                    const uint32_t es = lut[first + nibs];
-                    const int32_t ss = (int32_t)(int8_t)(es & 0xFFu) + (int32_t)(int8_t)((es >> 8) & 0xFFu);
-                    const int32_t st = s02 + s13;
-                    xrel += 4 * R * Rs + R * ss + Rs * st + pair[(first << 4) + (nib << 4) + nibs];
-                    rel1s += 4 * Rs + ss;
-                    Rs += (int32_t)((es >> 26) & 15u) - 4;
-                }
-                R += T;
-            }
-            if (!active) {  // lanes past the end of a short band add nothing
-                R = rel1e = rel1o = rel2e = rel2o = 0;
-                Rs = rel1s = xrel = 0;
-            }
+        auto one_row = [&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            uint32_t U[8], Us[8];
+            uint32_t su = 0, sue = 0, sus = 0, suse = 0;
+            uint32_t a2 = 0, a2e = 0, b2 = 0, b2e = 0;
+            int32_t R = row_offsets<r, true, FIRST>(lut, wk[r], U, a2, a2e, su, sue);
+            int32_t Rs = 0;
+            if (CROSS) Rs = row_offsets<r, false, FIRST>(lut, sk[r], Us, b2, b2e, sus, suse);
+            if (!active) R = Rs = 0;  // lanes past the end of a short band add nothing
             int32_t tot, tot_s = 0;
             const int32_t ex = wave_excl_scan_i32(R, tot);
-            const int64_t Ah = (int64_t)h0[4 * band + r] + carry[r] + ex;  // height before the block
-            const int64_t n = active ? 16 : 0;                               // sites per class
-            s1e += n * Ah + rel1e;
-            s1o += n * Ah + rel1o;
-            s2e += n * Ah * Ah + 2 * Ah * rel1e + rel2e;
-            s2o += n * Ah * Ah + 2 * Ah * rel1o + rel2o;
+            const int32_t A = h0r[r] + carry[r] + ex;  // height before the block
             carry[r] += tot;
+            int32_t As = 0;
             if (CROSS) {
                 const int32_t exs = wave_excl_scan_i32(Rs, tot_s);
-                const int64_t As = (int64_t)h0s[4 * band + r] + carry_s[r] + exs;
-                sts += 2 * n * Ah * As + Ah * rel1s + As * (int64_t)(rel1e + rel1o) + xrel;
+                As = h0sr[r] + carry_s[r] + exs;
                 carry_s[r] += tot_s;
             }
-        }
-    }
+            if (active) {
+                const int32_t sq = (int32_t)su - 2048, sqe = (int32_t)sue - 1024, sqo = sq - sqe;
+                lin_e += 16 * A + sqe;
+                lin_o += 16 * A + sqo;
+                quad_e += (int64_t)(2 * A) * (8 * A + sqe);
+                quad_o += (int64_t)(2 * A) * (8 * A + sqo);
+                u2 += a2;
+                u2e += a2e;
+                ue += sue;
+                uall += su;
+                rows += 1;
+                if (CROSS) {
+                    uint32_t x = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) x = __builtin_amdgcn_udot4(U[k], Us[k], x, false);
+                    uts += x;
+                    us_all += sus;
+                    xa += (int64_t)A * (32 * As + ((int32_t)sus - 2048)) + (int64_t)As * sq;
+                }
+            }
+        };
+        one_row(std::integral_constant<int, 0>());
+        one_row(std::integral_constant<int, 1>());
+        one_row(std::integral_constant<int, 2>());
+        one_row(std::integral_constant<int, 3>());
+    };
+    chunk(0u, std::true_type());
+    for (uint32_t base = 64; base < nbx; base += 64) chunk(base, std::false_type());
+    // sums of q and q^2 from those of u = q + 64 (16 sites per class per block row)
+    const int64_t n16 = 16 * (int64_t)rows;
+    const int64_t uo = (int64_t)uall - ue, u2o = (int64_t)u2 - u2e;
+    int64_t s1e = lin_e, s1o = lin_o;
+    int64_t s2e = quad_e + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
+    int64_t s2o = quad_o + (u2o - 128 * uo + 4096 * n16);
+    int64_t sts = 0;
+    if (CROSS) sts = xa + ((int64_t)uts - 64 * ((int64_t)uall + us_all) + 4096 * 2 * n16);
     s1e = wave_sum_i64(s1e);
     s1o = wave_sum_i64(s1o);
     s2e = wave_sum_i64(s2e);
@@ -1068,13 +1132,12 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
                                                                const int32_t *__restrict__ h0s, uint32_t L,
                                                                uint32_t nbx_log2, int64_t *__restrict__ partial)
 {
-    __shared__ uint32_t lut[32];
-    __shared__ int32_t pair[CROSS ? 512 : 1];
-    build_tables<CROSS>(lut, pair);
+    __shared__ __align__(8) uint32_t lut[512];
+    build_tables(lut);
     __syncthreads();
     const uint32_t band = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
     if (band >= (L >> 2)) return;
-    rows_band<CROSS>(lut, pair, words, h0, snap, h0s, band, nbx_log2,
+    rows_band<CROSS>(lut, words, h0, snap, h0s, band, nbx_log2,
                      partial + static_cast<uint64_t>(band) * kMomentFields);
 }
 
