@@ -17,23 +17,15 @@ import math
 import numpy as np
 import pytest
 
+from paper_1705_01022_amd import aging
+
 pytestmark = pytest.mark.gpu
 
 TIMES = [1, 2, 4, 8, 16, 32, 64, 128]
 
 
 def gpu_series(okpz, L, D, C, scheme, p, q, n, times, seed):
-    b = okpz.Batch()
-    lats = [b.lattice(L, D, D, C, C, scheme, seed=seed, stream=r) for r in range(n)]
-    out = np.zeros((n, len(times)))
-    series = b.series(times, p, q)
-    for i, obs in enumerate(series):
-        for r in range(n):
-            out[r, i] = obs[r][0]["w2"]
-    b.close()
-    for lat in lats:
-        lat.close()
-    return out
+    return aging.roughness(okpz, n, L, D, C, scheme, p, q, times, seed=seed).w2
 
 
 def seq_series(orc, L, p, q, n, times, seed):
@@ -49,16 +41,9 @@ def seq_series(orc, L, p, q, n, times, seed):
 
 
 def beta_eff(w2, times, i, j):
-    """Effective exponent (Eq. `eq:effexp`) of W = sqrt(<W^2>) between
-    times[i] < times[j], with its standard error from the sample means (delta
-    method, covariance of the two means taken from the runs)."""
-    n = w2.shape[0]
-    mi, mj = w2[:, i].mean(), w2[:, j].mean()
-    span = math.log(times[j] / times[i])
-    b = 0.5 * math.log(mj / mi) / span
-    c = np.cov(w2[:, i], w2[:, j]) / n
-    g = np.array([-0.5 / mi, 0.5 / mj])
-    return b, math.sqrt(float(g @ c @ g)) / span
+    """Effective growth exponent (Eq. `eq:effexp`) of W = sqrt(<W^2>) between
+    times[i] < times[j], with its standard error."""
+    return aging.effective_exponent(times, w2, j, i, power=0.5)
 
 
 def test_roughness_growth_matches_sequential_rs(okpz, orc):
