@@ -274,8 +274,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the method's lattice lives on one "
-              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the benchmark runs on exactly one GPU (the lattice and its kernels live on one "
+              "MI355X; sharding across GPUs is a design, not an implementation); --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: one process only", file=sys.stderr)
