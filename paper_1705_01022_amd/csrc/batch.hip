@@ -3,10 +3,22 @@
 //
 // Work items are (lattice, generation g = 4 * MCS-in-launch + step, tile).
 // They are numbered generation-major and handed out in that order through a
-// global ticket counter; an item of lattice r and generation g may start once
-// all g * tiles(r) items of r's earlier generations have finished (the same
-// device-wide step order a per-step launch gives, Sec. 3.1, but per lattice,
-// so the steps of different lattices overlap).  An item only ever waits for
+// global ticket counter.  An item of lattice r, generation g and tile t may
+// start once generation g - 1 has finished on every tile of r whose items can
+// touch a memory word that (g, t) touches: a tile's items stay inside its
+// "extended region", its 2D x 2D sites and the +1 halo widened to whole
+// 32-site words and 4-row bands, and the neighbourhood is every tile of the
+// previous generation's tiling whose extended region meets t's (the 3 x 3
+// tiles around t for D >= 32 in the same tiling; around the old tile holding
+// t's corner, one wider, after a new random origin).  It also waits for
+// generation g - 1 of tile t itself, so every tile finishes its generations in
+// order and one counter per tile ("stamp": generations finished) describes
+// it.  By induction over g, every earlier item touching a word of t's extended
+// region has finished when (g, t) starts (a site there lies in the extended
+// region of one of the neighbourhood tiles of generation g - 1, which waited
+// for the same in its own), and two items running at once never share a word.
+// So the result is that of the device-wide step order of Sec. 3.1, while
+// steps overlap across tiles of one lattice and across lattices.  An item only ever waits for
 // items with smaller tickets, which are held by running workgroups, so the
 // queue always drains; every wait is also bounded in time and a timed-out
 // wait stops the whole launch with an error flag.
@@ -49,7 +61,7 @@ struct BatchArgs {
     uint32_t nphase;
     uint64_t total_items;
     const uint64_t *mcs_base;  // MCS count of each lattice at the launch
-    uint32_t *done;            // finished items per lattice (zeroed before the launch)
+    uint32_t *stamp;           // per tile (tile_prefix order): generations finished in this launch
     unsigned long long *ticket;
     uint32_t *error;      // sticky: set when a dependency wait timed out
     uint64_t wait_ticks;  // wait limit in wall-clock ticks
@@ -70,62 +82,143 @@ __device__ __forceinline__ uint32_t perm_element(uint32_t pick, uint32_t k)
     return e;
 }
 
+// Tiling origin of MCS m of a lattice (as the host draws it) and the word w
+// whose third element picks the order of the domain sets.
+__device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint32_t &ox, uint32_t &oy)
+{
+    const u32x4 w = philox4x32_10(S.a.key0, S.a.key1, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)(m << 2));
+    ox = w.x & S.a.L_mask;
+    oy = w.y & S.a.L_mask;
+    if (S.origin_mode == OKPZ_ORIGIN_FIXED) ox = oy = 0u;
+    if (S.origin_mode == OKPZ_ORIGIN_COARSE) {
+        ox &= ~3u;
+        oy &= ~3u;
+    }
+    return w;
+}
+
 // COLS: every lattice of the launch is DB with lanes x CPT cells per domain
 // and at most 64 cells per row, so the column-mapped sweep serves them all.
 template <int SCHEME, int CPT, bool COLS>
 __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
 {
     extern __shared__ uint32_t smem[];
-    __shared__ uint32_t cmd[4];  // lattice, tile, generation, stop
+    // lattice, tile, generation, stop; the neighbourhood to wait for: first
+    // column, columns, first row, rows
+    __shared__ uint32_t cmd[8];
     const uint32_t tid = threadIdx.x;
-    uint32_t my_slot = 0;
+    uint32_t my_stamp = 0;
     for (;;) {
-        if (tid == 0) {
-            uint32_t r = 0, t = 0, g = 0, stop = 0;
-            const unsigned long long i = atomicAdd(B.ticket, 1ull);
-            if (i >= B.total_items || __hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                stop = 1;
-            } else {
-                uint32_t lo = 0, hi = B.nphase;
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (B.phases[mid].first_item <= i) lo = mid; else hi = mid;
-                }
-                const BatchPhase ph = B.phases[lo];
-                const uint64_t rel = i - ph.first_item;
-                g = ph.gen_begin + (uint32_t)(rel / ph.items_per_gen);
-                const uint32_t off = (uint32_t)(rel % ph.items_per_gen);
-                lo = 0;
-                hi = ph.nslots;
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (B.tile_prefix[mid] <= off) lo = mid; else hi = mid;
-                }
-                r = lo;
-                t = off - B.tile_prefix[r];
-                const uint32_t need = g * B.slots[r].ntiles;
-                if (need > 0u) {
-                    const uint64_t t0 = wall_clock64();
-                    while (__hip_atomic_load(&B.done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        if (__hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            stop = 1;
-                            break;
-                        }
-                        if (wall_clock64() - t0 > B.wait_ticks) {
-                            atomicOr(B.error, 1u);
-                            stop = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
+        if (tid < 64u) {
+            if (tid == 0) {
+                uint32_t r = 0, t = 0, g = 0, stop = 0;
+                uint32_t cx0 = 0, ncol = 0, cy0 = 0, nrow = 0;
+                const unsigned long long i = atomicAdd(B.ticket, 1ull);
+                if (i >= B.total_items || __hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    stop = 1;
+                } else {
+                    uint32_t lo = 0, hi = B.nphase;
+                    while (hi - lo > 1u) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (B.phases[mid].first_item <= i) lo = mid; else hi = mid;
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    const BatchPhase ph = B.phases[lo];
+                    const uint64_t rel = i - ph.first_item;
+                    g = ph.gen_begin + (uint32_t)(rel / ph.items_per_gen);
+                    const uint32_t off = (uint32_t)(rel % ph.items_per_gen);
+                    lo = 0;
+                    hi = ph.nslots;
+                    while (hi - lo > 1u) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (B.tile_prefix[mid] <= off) lo = mid; else hi = mid;
+                    }
+                    r = lo;
+                    t = off - B.tile_prefix[r];
+                    if (g > 0u) {
+                        // The tiles of generation g - 1 whose memory footprint can
+                        // share a word with this item's: a tile's items touch the
+                        // words of its 2D x 2D sites plus the +1 halo, widened to
+                        // whole 32-site words (31 sites on either side) and 4-row
+                        // bands (3 rows), so tiles further than 1 + 31/Dx columns or
+                        // 1 + 3/Dy rows apart never share a word.  First step of an
+                        // MCS (new random origin): around the previous tiling's tile
+                        // holding this tile's corner, one more tile on the far side.
+                        const BatchSlot &S = B.slots[r];
+                        const uint32_t lx = S.a.log2ntx, ntx = 1u << lx, nty = S.ntiles >> lx;
+                        uint32_t tx = t & (ntx - 1u), ty = t >> lx;
+                        const uint32_t ex = 31u / S.a.Dx, ey = 3u / S.a.Dy;
+                        uint32_t hix = 1u + ex, hiy = 1u + ey;
+                        if ((g & 3u) == 0u) {
+                            const uint64_t m = B.mcs_base[r] + (g >> 2);
+                            uint32_t ox, oy, oxp, oyp;
+                            (void)mcs_origin(S, m, ox, oy);
+                            (void)mcs_origin(S, m - 1u, oxp, oyp);
+                            const uint32_t sx = (uint32_t)__builtin_ctz(2u * S.a.Dx);
+                            const uint32_t sy = (uint32_t)__builtin_ctz(2u * S.a.Dy);
+                            tx = (((ox + (tx << sx)) - oxp) & S.a.L_mask) >> sx;
+                            ty = (((oy + (ty << sy)) - oyp) & S.a.L_mask) >> sy;
+                            hix += 1u;
+                            hiy += 1u;
+                        }
+                        // columns tx - 1 - ex .. tx + hix (all of them when that wraps)
+                        cx0 = (tx + ntx - ((1u + ex) & (ntx - 1u))) & (ntx - 1u);
+                        ncol = 2u + ex + hix;
+                        cy0 = (ty + nty - ((1u + ey) & (nty - 1u))) & (nty - 1u);
+                        nrow = 2u + ey + hiy;
+                        if (ncol >= ntx) {
+                            cx0 = 0u;
+                            ncol = ntx;
+                        }
+                        if (nrow >= nty) {
+                            cy0 = 0u;
+                            nrow = nty;
+                        }
+                    }
                 }
+                cmd[0] = r;
+                cmd[1] = t;
+                cmd[2] = g;
+                cmd[3] = stop;
+                cmd[4] = cx0;
+                cmd[5] = ncol;
+                cmd[6] = cy0;
+                cmd[7] = nrow;
+                my_stamp = stop ? 0u : B.tile_prefix[r] + t;
             }
-            cmd[0] = r;
-            cmd[1] = t;
-            cmd[2] = g;
-            cmd[3] = stop;
-            my_slot = r;
+            wave_order();
+            // The first wave waits for the neighbourhood, one stamp per lane (and
+            // for tile t itself, so that each tile finishes its generations in
+            // order and its stamp counts them), every wait bounded in time.
+            const uint32_t g = cmd[2];
+            if (!cmd[3] && g > 0u) {
+                const uint32_t r = cmd[0], t = cmd[1], cx0 = cmd[4], ncol = cmd[5], cy0 = cmd[6], nrow = cmd[7];
+                const BatchSlot &S = B.slots[r];
+                const uint32_t lx = S.a.log2ntx, ntx = 1u << lx, nty = S.ntiles >> lx;
+                const uint32_t *st = B.stamp + B.tile_prefix[r];
+                const uint32_t nwait = ncol * nrow + 1u;
+                const uint64_t t0 = wall_clock64();
+                bool bad = false;
+                for (uint32_t nb = tid; nb < nwait; nb += 64u) {
+                    const uint32_t nx = (cx0 + nb % ncol) & (ntx - 1u);
+                    const uint32_t ny = (cy0 + nb / ncol) & (nty - 1u);
+                    const uint32_t *sp = nb + 1u < nwait ? st + ((ny << lx) | nx) : st + t;
+                    while (!bad && __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < g) {
+                        if (__hip_atomic_load(B.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            bad = true;
+                        } else if (wall_clock64() - t0 > B.wait_ticks) {
+                            atomicOr(B.error, 1u);
+                            bad = true;
+                        } else {
+                            __builtin_amdgcn_s_sleep(2);
+                        }
+                    }
+                }
+                const uint64_t any_bad = __ballot(bad);  // every lane of the wave takes part
+                // the earlier steps' words, written by other workgroups, become visible
+                // (the cache invalidation covers the whole workgroup's caches)
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (tid == 0 && any_bad) cmd[3] = 1u;
+            }
         }
         __syncthreads();
         if (cmd[3]) break;
@@ -137,13 +230,8 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
         // MCS draw of the lattice's MCS m (as on the host): origin and set order
         const uint64_t m = B.mcs_base[r] + (g >> 2);
         const uint32_t k = g & 3u;
-        const u32x4 w = philox4x32_10(A.key0, A.key1, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)(m << 2));
-        uint32_t ox = w.x & A.L_mask, oy = w.y & A.L_mask;
-        if (S.origin_mode == OKPZ_ORIGIN_FIXED) ox = oy = 0u;
-        if (S.origin_mode == OKPZ_ORIGIN_COARSE) {
-            ox &= ~3u;
-            oy &= ~3u;
-        }
+        uint32_t ox, oy;
+        const u32x4 w = mcs_origin(S, m, ox, oy);
         const uint32_t set = perm_element((uint32_t)(((uint64_t)w.z * 24u) >> 32), k);
         A.ox = ox;
         A.oy = oy;
@@ -151,9 +239,9 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
         A.set_b = set >> 1;
         A.c3 = (uint32_t)(m << 2) | k;
         // Visibility of the earlier steps' words, written by other workgroups:
-        // thread 0 took the agent-scope acquire after its wait, before the
-        // barrier above (it invalidates the caches this workgroup reads through,
-        // which all its waves share).
+        // the first wave took the agent-scope acquire after its waits, before
+        // the barrier above (it invalidates the caches this workgroup reads
+        // through, which all its waves share).
         if constexpr (COLS) {
             if (S.accept)
                 sweep_db_columns<true, CPT, 0>(A, smem, tile);
@@ -165,19 +253,19 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
             else
                 sweep_tile<SCHEME, false, CPT, false>(A, smem, tile);
         }
-        // Publish this tile's words before counting the item as done: every
-        // lane waits until its own stores are acknowledged, the barrier orders
-        // them before thread 0, whose agent-scope release increment writes them
-        // back for the other dies (once per item, not once per wave).
+        // Publish this tile's words before stamping the tile with generation
+        // g done: every lane waits until its own stores are acknowledged, the
+        // barrier orders them before thread 0, whose agent-scope release store
+        // writes them back for the other dies (once per item, not once per wave).
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&B.done[my_slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(&B.stamp[my_stamp], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-__global__ void batch_reset_kernel(uint32_t *done, uint32_t n, unsigned long long *ticket)
+__global__ void batch_reset_kernel(uint32_t *stamp, uint32_t n, unsigned long long *ticket)
 {
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) stamp[i] = 0u;
     if (threadIdx.x == 0) *ticket = 0ull;
 }
 
@@ -286,10 +374,10 @@ struct okpz_batch {
     uint32_t *d_prefix = nullptr;
     BatchPhase *d_phases = nullptr;
     uint64_t *d_mcs = nullptr;
-    uint32_t *d_done = nullptr;
+    uint32_t *d_stamp = nullptr;
     unsigned long long *d_ticket = nullptr;
     uint32_t *d_error = nullptr;
-    size_t cap_slots = 0, cap_phases = 0;
+    size_t cap_slots = 0, cap_phases = 0, cap_tiles = 0;
     // pinned staging for the tables (rewritten only after a stream sync)
     uint8_t *h_stage = nullptr;
     size_t stage_cap = 0;
@@ -329,7 +417,7 @@ void batch_release(okpz_batch *b)
     (void)hipFree(b->d_prefix);
     (void)hipFree(b->d_phases);
     (void)hipFree(b->d_mcs);
-    (void)hipFree(b->d_done);
+    (void)hipFree(b->d_stamp);
     (void)hipFree(b->d_ticket);
     (void)hipFree(b->d_error);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
@@ -343,25 +431,30 @@ void batch_release(okpz_batch *b)
     delete b;
 }
 
-int grow_tables(okpz_batch *b, size_t nslots, size_t nphases)
+int grow_tables(okpz_batch *b, size_t nslots, size_t nphases, size_t ntiles)
 {
     if (nslots > b->cap_slots) {
         const size_t cap = std::max<size_t>(nslots, 2 * b->cap_slots);
         (void)hipFree(b->d_slots);
         (void)hipFree(b->d_prefix);
         (void)hipFree(b->d_mcs);
-        (void)hipFree(b->d_done);
         b->d_slots = nullptr;
         b->d_prefix = nullptr;
         b->d_mcs = nullptr;
-        b->d_done = nullptr;
         b->cap_slots = 0;
         if (hipMalloc(&b->d_slots, cap * sizeof(BatchSlot)) != hipSuccess ||
             hipMalloc(&b->d_prefix, (cap + 1) * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&b->d_mcs, cap * sizeof(uint64_t)) != hipSuccess ||
-            hipMalloc(&b->d_done, cap * sizeof(uint32_t)) != hipSuccess)
+            hipMalloc(&b->d_mcs, cap * sizeof(uint64_t)) != hipSuccess)
             return OKPZ_ENOMEM;
         b->cap_slots = cap;
+    }
+    if (ntiles > b->cap_tiles) {
+        const size_t cap = std::max<size_t>(ntiles, 2 * b->cap_tiles);
+        (void)hipFree(b->d_stamp);
+        b->d_stamp = nullptr;
+        b->cap_tiles = 0;
+        if (hipMalloc(&b->d_stamp, cap * sizeof(uint32_t)) != hipSuccess) return OKPZ_ENOMEM;
+        b->cap_tiles = cap;
     }
     if (nphases + 1 > b->cap_phases) {
         const size_t cap = std::max<size_t>(nphases + 1, 2 * b->cap_phases);
@@ -422,14 +515,14 @@ const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols)
 // persistent kernel, advance the per-lattice MCS counts.
 struct LaunchPlan {
     const void *fn;
-    uint32_t threads, grid, nslots;
+    uint32_t threads, grid, nslots, ntiles;
     size_t lds;
     BatchArgs args;
 };
 
 int enqueue(okpz_batch *b, const LaunchPlan &lp)
 {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, b->stream, b->d_done, lp.nslots, b->d_ticket);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1024), 0, b->stream, b->d_stamp, lp.ntiles, b->d_ticket);
     void *kargs[] = {const_cast<BatchArgs *>(&lp.args)};
     HIP_TRY(hipLaunchKernel(lp.fn, dim3(lp.grid), dim3(lp.threads), kargs, lp.lds, b->stream));
     hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, b->stream, b->d_mcs, b->d_slots, lp.nslots);
@@ -658,7 +751,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
 
     if (!same_tables || !mcs_current) {
         HIP_TRY(hipStreamSynchronize(b->stream));  // the staging buffer may still be read
-        const int rc = grow_tables(b, n, phases.size());
+        const int rc = grow_tables(b, n, phases.size(), prefix[n]);
         if (rc != OKPZ_OK) return rc;
         uint8_t *st = b->h_stage;
         BatchSlot *hs = reinterpret_cast<BatchSlot *>(st);
@@ -684,6 +777,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     lp.threads = nt;
     lp.grid = grid;
     lp.nslots = n;
+    lp.ntiles = prefix[n];
     lp.lds = lds;
     lp.args.slots = b->d_slots;
     lp.args.tile_prefix = b->d_prefix;
@@ -691,7 +785,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     lp.args.nphase = nphase;
     lp.args.total_items = total;
     lp.args.mcs_base = b->d_mcs;
-    lp.args.done = b->d_done;
+    lp.args.stamp = b->d_stamp;
     lp.args.ticket = b->d_ticket;
     lp.args.error = b->d_error;
     {

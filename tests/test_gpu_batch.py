@@ -123,6 +123,41 @@ def test_batch_equals_plain_runs(okpz):
     b.close()
 
 
+# Long runs of lone lattices and pairs, where the steps of one lattice overlap
+# most (few tiles per step): (L, D, C, scheme, p, q, MCS, members).  D from 8
+# (footprint margins span 3 tiles more: 31 // 8) to 256 (one tile either side).
+LONG = [
+    (2048, 256, 8, 1, 0.95, 0.05, 300, 1),
+    (1024, 256, 8, 0, 1.0, 0.0, 400, 2),
+    (512, 64, 8, 2, 0.7, 0.2, 300, 1),
+    (512, 16, 8, 1, 1.0, 0.0, 200, 1),
+    (256, 8, 4, 0, 0.5, 0.5, 300, 2),
+    (1024, 32, 8, 1, 0.95, 0.05, 200, 3),
+]
+
+
+@pytest.mark.parametrize("case", LONG, ids=lambda c: "L%d_D%d_C%d_s%d_n%d" % (c[0], c[1], c[2], c[3], c[7]))
+def test_batch_long_runs_equal_plain(okpz, case):
+    """The steps of one lattice overlap across tiles inside a batch launch
+    (each tile waits only for the tiles whose memory words it can share); over
+    hundreds of MCS, with random origins that move the tiling every MCS, every
+    member still equals the lattice run alone step by step."""
+    L, D, C, scheme, p, q, mcs, n = case
+    b = okpz.Batch()
+    batched = [b.lattice(L, D, D, C, C, scheme, seed=3, stream=40 + i) for i in range(n)]
+    alone = [okpz.Lattice(L, D, D, C, C, scheme, seed=3, stream=40 + i) for i in range(n)]
+    b.run([mcs] * n, p, q)
+    b.sync()
+    for lat in alone:
+        lat.run(mcs, p, q)
+    for x, y in zip(batched, alone):
+        assert x.mcs == y.mcs == mcs
+        assert np.array_equal(x.words(), y.words())
+    b.close()
+    for lat in batched + alone:
+        lat.close()
+
+
 def test_batch_rejects_bad_arguments(okpz):
     b = okpz.Batch()
     a = b.lattice(64, 16, 16, 8, 8, 0)
