@@ -268,9 +268,10 @@ int okpz_device_words(okpz_lattice *lat, void **dev_words, size_t *nbytes);
 int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs);
 
 /*
- * Workgroup size of the device-step kernel: 64, 128 or 256 threads, or 0 for
- * the default (256).  Each thread then updates ncell / threads thread cells
- * (at most 16, else OKPZ_EINVAL).  A physical mapping only: the simulated
+ * Workgroup size of the device-step kernel: 64, 128, 256 or 512 threads, or
+ * 0 for the default (512 when a device step has fewer tiles than four per
+ * compute unit, else 256).  Each thread then updates ncell / threads thread
+ * cells (at most 16, else OKPZ_EINVAL).  A physical mapping only: the simulated
  * lattice does not depend on it (every random draw is keyed by cell, not by
  * thread).  Chosen by an autotuner per domain shape.
  */
@@ -345,7 +346,9 @@ int okpz_batch_size(const okpz_batch *batch, uint32_t *nslots);
 
 /*
  * Launch shape (physical mapping only; results do not depend on it):
- * threads per workgroup (64, 128, 256, or 0 = 256), persistent workgroups
+ * threads per workgroup (64, 128, 256, 512, or 0: enough lanes for the
+ * largest domain's cells, at most 256, or 512 when the launch has fewer
+ * tiles per step than four per compute unit), persistent workgroups
  * (0 = as many as fit on the device at once), use_graph (capture and replay
  * the launch).  Chosen by the autotuner of the Python layer.
  */

@@ -537,7 +537,8 @@ class Batch:
         fastest.  Every candidate's MCS really advance the members (results do
         not depend on the shape).  Returns {candidate: ms} and the choice."""
         if candidates is None:
-            candidates = [(256, 1.0, True), (128, 1.0, True), (256, 0.5, True), (256, 1.0, False)]
+            candidates = [(256, 1.0, True), (128, 1.0, True), (512, 1.0, True), (256, 0.5, True),
+                          (256, 1.0, False)]
         full = self._full_grid()
         times = {}
         for threads, frac, graph in candidates:

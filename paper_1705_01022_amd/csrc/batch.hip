@@ -100,7 +100,7 @@ __device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint
 // COLS: every lattice of the launch is DB with lanes x CPT cells per domain
 // and at most 64 cells per row, so the column-mapped sweep serves them all.
 template <int SCHEME, int CPT, bool COLS>
-__global__ void __launch_bounds__(256) batch_kernel(BatchArgs B)
+__global__ void __launch_bounds__(kMaxStepThreads) batch_kernel(BatchArgs B)
 {
     extern __shared__ uint32_t smem[];
     // lattice, tile, generation, stop; the neighbourhood to wait for: first
@@ -621,7 +621,7 @@ int okpz_batch_size(const okpz_batch *b, uint32_t *nslots)
 int okpz_batch_config(okpz_batch *b, uint32_t threads, uint32_t grid, int use_graph)
 {
     if (!b) return OKPZ_EINVAL;
-    if (threads != 0 && threads != 64 && threads != 128 && threads != 256) return OKPZ_EINVAL;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512) return OKPZ_EINVAL;
     if (use_graph && !b->stream) return OKPZ_EINVAL;
     b->threads = threads;
     b->grid = grid;
@@ -636,6 +636,8 @@ namespace {
 
 // One persistent launch (reset, batch kernel, advance) for the members with
 // n_mcs[s] > 0, already validated; 4 * n_mcs * tiles < 2^31 for each.
+uint64_t tiles_of(const okpz_params &prm) { return (uint64_t)(prm.L / (2 * prm.dom_x)) * (prm.L / (2 * prm.dom_y)); }
+
 int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const double *q)
 {
     const size_t ns = b->slots.size();
@@ -652,8 +654,14 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     for (int32_t s : order) max_cells = std::max(max_cells, cells_of(b->slots[s]->prm));
     uint32_t nt = b->threads;
     if (nt == 0) {
+        uint64_t tiles = 0;
+        for (int32_t s : order) tiles += tiles_of(b->slots[s]->prm);
+        int dev = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const uint32_t cap = default_threads(tiles, (uint32_t)std::max(cus, 1));
         nt = 64;
-        while (nt < 256u && nt < max_cells) nt *= 2;
+        while (nt < cap && nt < max_cells) nt *= 2;
     }
     uint32_t cpt = 1;
     while (cpt * nt < max_cells) cpt *= 2;
@@ -845,7 +853,6 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     return OKPZ_OK;
 }
 
-uint64_t tiles_of(const okpz_params &prm) { return (uint64_t)(prm.L / (2 * prm.dom_x)) * (prm.L / (2 * prm.dom_y)); }
 
 }  // namespace
 

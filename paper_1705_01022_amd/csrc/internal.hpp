@@ -65,7 +65,8 @@ struct okpz_lattice {
     bool has_snap = false;
     uint64_t snap_mcs = 0;
     __int128 snap_s1 = 0;
-    uint32_t threads = 0;  // device-step workgroup size (0: default)
+    uint32_t threads = 0;  // device-step workgroup size (0: by the number of tiles per step)
+    uint32_t cus = 0;      // compute units of the device
     // timing
     bool timing = false;
     std::vector<okpz_host::TimedPair> pairs;
@@ -234,6 +235,14 @@ inline void end_timed(okpz_lattice *lat, TimedPair &tp)
 // Workgroup shape of the device step: `threads` lanes (64, 128 or 256; 0
 // picks 256) with ncell / threads cells each (at most 16), fewer lanes when
 // the domain has fewer cells.  Results do not depend on the shape.
+// Lanes per device-step workgroup when none is configured: 256, or 512 when a
+// step has fewer than 4 tiles per compute unit (more lanes then share the few
+// tiles; with more tiles 256-lane workgroups keep more of them resident).
+inline uint32_t default_threads(uint64_t ntiles, uint32_t cus)
+{
+    return ntiles < 4ull * cus ? 512u : 256u;
+}
+
 inline void step_shape(uint32_t ncell, uint32_t threads, uint32_t &cpt, uint32_t &nt)
 {
     nt = threads ? threads : 256u;

@@ -837,8 +837,12 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
     copy_window<false>(A, lds, orig, X0 >> 5, Y0 >> 2);
 }
 
+// Largest device-step workgroup: 512 lanes (two cells each for 1024-cell
+// domains), used when a step has few tiles, so that more lanes share them.
+constexpr int kMaxStepThreads = 512;
+
 template <bool ACCEPT, int CPT, int FL>
-__global__ void __launch_bounds__(256) step_db_columns_kernel(StepArgs A)
+__global__ void __launch_bounds__(kMaxStepThreads) step_db_columns_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];
     sweep_db_columns<ACCEPT, CPT, FL>(A, smem, blockIdx.x);
@@ -848,7 +852,7 @@ __global__ void __launch_bounds__(256) step_db_columns_kernel(StepArgs A)
 // than one cell per lane the workgroup shape divides the domain's cells
 // exactly; one cell per lane may leave lanes idle.
 template <int SCHEME, bool ACCEPT, int CPT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs A)
+__global__ void __launch_bounds__(kMaxStepThreads) step_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];
     sweep_tile<SCHEME, ACCEPT, CPT, (CPT > 1)>(A, smem, blockIdx.x);

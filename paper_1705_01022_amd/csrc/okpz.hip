@@ -85,10 +85,10 @@ int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
 {
     const okpz_params &p = lat->prm;
     const uint32_t ncell = a.ncell;
-    uint32_t cpt, nt;
-    step_shape(ncell, lat->threads, cpt, nt);
-    if (cpt > 16) return OKPZ_EINVAL;
     const uint32_t ntiles = (p.L / (2 * p.dom_x)) * (p.L / (2 * p.dom_y));
+    uint32_t cpt, nt;
+    step_shape(ncell, lat->threads ? lat->threads : default_threads(ntiles, lat->cus), cpt, nt);
+    if (cpt > 16) return OKPZ_EINVAL;
     const size_t lds = step_lds_bytes(p, nt * cpt);
     int rc;
     switch (p.block_scheme * 2 + (accept ? 1 : 0)) {
@@ -324,6 +324,13 @@ int create_common(const okpz_params *params, void *hip_stream, void *dev_words, 
         release(lat);
         return OKPZ_ENOMEM;
     }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        release(lat);
+        return OKPZ_EHIP;
+    }
+    lat->cus = (uint32_t)std::max(cus, 1);
     const int frc = fill_flat(lat);
     if (frc != OKPZ_OK) {
         release(lat);
@@ -752,7 +759,7 @@ int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs)
 int okpz_set_threads(okpz_lattice *lat, uint32_t threads)
 {
     if (!lat) return OKPZ_EINVAL;
-    if (threads != 0 && threads != 64 && threads != 128 && threads != 256) return OKPZ_EINVAL;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512) return OKPZ_EINVAL;
     const uint32_t ncell = (lat->prm.dom_x / lat->prm.cell_x) * (lat->prm.dom_y / lat->prm.cell_y);
     uint32_t cpt, nt;
     step_shape(ncell, threads, cpt, nt);

@@ -64,7 +64,8 @@ def test_batch_matches_oracle(okpz, orc, scheme):
     b.close()
 
 
-@pytest.mark.parametrize("threads,grid,graph", [(64, 0, True), (128, 1, False), (256, 3, True), (256, 0, False)])
+@pytest.mark.parametrize("threads,grid,graph", [(64, 0, True), (128, 1, False), (256, 3, True), (256, 0, False),
+                                                (512, 0, True), (512, 2, False)])
 def test_batch_launch_shape_does_not_change_results(okpz, orc, threads, grid, graph):
     b, lats, mirrors = make_batch(okpz, orc, 1)
     b.config(threads, grid, graph)
@@ -192,4 +193,15 @@ def test_batch_db_column_sweep(okpz, orc, threads):
     b.config(threads, 0, True)
     run_both(b, lats, mirrors, mix, [m[5] for m in mix])
     run_both(b, lats, mirrors, mix, [1, 2, 1, 1])
+    b.close()
+
+
+@pytest.mark.parametrize("threads", [512, 256])
+def test_batch_db_column_sweep_1024_cells(okpz, orc, threads):
+    """1024-cell DB domains (D = 256, TC = 1,1) in the column-mapped sweep with
+    512 lanes x 2 cells and 256 lanes x 4 cells: the oracle's results."""
+    mix = [(512, 256, 8, 0.95, 0.05, 2), (512, 256, 8, 1.0, 0.0, 3)]
+    b, lats, mirrors = make_batch(okpz, orc, 1, mix)
+    b.config(threads, 0, True)
+    run_both(b, lats, mirrors, mix, [m[5] for m in mix])
     b.close()

@@ -215,7 +215,7 @@ def test_workgroup_shape_does_not_change_results(okpz, orc, scheme, pq, shape):
     for m in range(3):
         e.mcs(ref, m)
     ncell = (Dx // Cx) * (Dy // Cy)
-    for threads in (0, 64, 128, 256):
+    for threads in (0, 64, 128, 256, 512):
         with lattice(okpz, L=L, Dx=Dx, Dy=Dy, Cx=Cx, Cy=Cy, scheme=scheme) as lat:
             if ncell // threads > 16 if threads else False:
                 with pytest.raises(okpz.OkpzError):
