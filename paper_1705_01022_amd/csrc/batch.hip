@@ -99,7 +99,10 @@ __device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint
 
 // COLS: every lattice of the launch is DB with lanes x CPT cells per domain
 // and at most 64 cells per row, so the column-mapped sweep serves them all.
-template <int SCHEME, int CPT, bool COLS>
+// FL > 0 (with COLS): every lattice also draws 2^FL-bit lane fields, with
+// acceptance draws iff FL = 4 and a whole number of Philox blocks of rounds,
+// so the sweep with the rounds of one block unrolled serves them all.
+template <int SCHEME, int CPT, bool COLS, int FL>
 __global__ void __launch_bounds__(kMaxStepThreads) batch_kernel(BatchArgs B)
 {
     extern __shared__ uint32_t smem[];
@@ -242,7 +245,9 @@ __global__ void __launch_bounds__(kMaxStepThreads) batch_kernel(BatchArgs B)
         // the first wave took the agent-scope acquire after its waits, before
         // the barrier above (it invalidates the caches this workgroup reads
         // through, which all its waves share).
-        if constexpr (COLS) {
+        if constexpr (COLS && FL > 0) {
+            sweep_db_columns<FL == 4, CPT, FL>(A, smem, tile);
+        } else if constexpr (COLS) {
             if (S.accept)
                 sweep_db_columns<true, CPT, 0>(A, smem, tile);
             else
@@ -476,13 +481,13 @@ int grow_tables(okpz_batch *b, size_t nslots, size_t nphases, size_t ntiles)
     return OKPZ_OK;
 }
 
-template <int SCHEME, int CPT, bool COLS>
+template <int SCHEME, int CPT, bool COLS, int FL = 0>
 const void *batch_fn()
 {
-    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT, COLS>);
+    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT, COLS, FL>);
 }
 
-const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols)
+const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols, int fl)
 {
 #define OKPZ_BATCH_CASES(S)                          \
     switch (cpt) {                                   \
@@ -492,6 +497,22 @@ const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols)
     case 8: return batch_fn<S, 8, false>();          \
     case 16: return batch_fn<S, 16, false>();        \
     default: return nullptr;                         \
+    }
+    if (cols && scheme == kDB && fl == 4) {
+        switch (cpt) {
+        case 2: return batch_fn<kDB, 2, true, 4>();
+        case 4: return batch_fn<kDB, 4, true, 4>();
+        case 8: return batch_fn<kDB, 8, true, 4>();
+        default: break;
+        }
+    }
+    if (cols && scheme == kDB && fl == 3) {
+        switch (cpt) {
+        case 2: return batch_fn<kDB, 2, true, 3>();
+        case 4: return batch_fn<kDB, 4, true, 3>();
+        case 8: return batch_fn<kDB, 8, true, 3>();
+        default: break;
+        }
     }
     if (cols && scheme == kDB) {
         switch (cpt) {
@@ -723,7 +744,16 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     }
     const uint32_t nphase = (uint32_t)phases.size() - 1;
 
-    const void *fn = batch_kernel_for(b->scheme, cpt, cols);
+    // one lane-field width for every member: the sweep with unrolled rounds
+    int fl = 0;
+    if (cols && cpt <= 8) {
+        fl = slots[0].accept ? 4 : 3;
+        for (uint32_t i = 0; i < n; ++i)
+            if ((int)slots[i].a.F_log2 != fl || (slots[i].accept != 0) != (fl == 4) ||
+                slots[i].a.rounds % (128u >> fl) != 0u)
+                fl = 0;
+    }
+    const void *fn = batch_kernel_for(b->scheme, cpt, cols, fl);
     if (!fn) return OKPZ_EINVAL;
     if (lds > 64u * 1024u)
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLds - kStaticLds)));
@@ -748,7 +778,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         k += sizeof(uint32_t) * (n + 1);
         std::memcpy(k, phases.data(), sizeof(BatchPhase) * phases.size());
         k += sizeof(BatchPhase) * phases.size();
-        const uint32_t shape[4] = {nt, cpt | (cols ? 0x100u : 0u), grid, b->use_graph ? 1u : 0u};
+        const uint32_t shape[4] = {nt, cpt | (cols ? 0x100u : 0u) | ((uint32_t)fl << 16), grid, b->use_graph ? 1u : 0u};
         std::memcpy(k, shape, sizeof(shape));
     }
     std::vector<int32_t> table_slot(order.begin(), order.end());
