@@ -349,8 +349,9 @@ int okpz_batch_size(const okpz_batch *batch, uint32_t *nslots);
  * threads per workgroup (64, 128, 256, 512, or 0: enough lanes for the
  * largest domain's cells, at most 256, or 512 when the launch has fewer
  * tiles per step than four per compute unit), persistent workgroups
- * (0 = as many as fit on the device at once), use_graph (capture and replay
- * the launch).  Chosen by the autotuner of the Python layer.
+ * (0 = as many as fit on the device at once, but no more than the members'
+ * tiles in one step), use_graph (capture and replay the launch).  Chosen by
+ * the autotuner of the Python layer.
  */
 int okpz_batch_config(okpz_batch *batch, uint32_t threads, uint32_t grid, int use_graph);
 

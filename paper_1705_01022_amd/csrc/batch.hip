@@ -764,6 +764,10 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         grid = (uint32_t)std::max(1, per_cu * cus);
+        // no more workgroups than tiles in one step of all members: a workgroup
+        // beyond them would only wait for the next step's dependencies while
+        // sharing its compute unit with a working one
+        grid = std::min(grid, prefix[n]);
     }
     grid = (uint32_t)std::min<uint64_t>(grid, total);
 
