@@ -37,8 +37,8 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # they were taken on (hash of the files below).
 DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/okpz.hip",
                   "paper_1705_01022_amd/csrc/philox.hpp", "paper_1705_01022_amd/csrc/internal.hpp")
-MEASURED_TRAFFIC = {"sources": "5092f2cd4b8ca052", "workload": "L131072",
-                    "fetch_kib": 799067.7, "write_kib": 1198080.0, "fetch_scale": 2.00, "write_scale": 1.00}
+MEASURED_TRAFFIC = {"sources": "36160a869c95783a", "workload": "L131072",
+                    "fetch_kib": 799071.0, "write_kib": 1198080.0, "fetch_scale": 2.00, "write_scale": 1.00}
 
 
 def device_sources_hash() -> str:
@@ -61,8 +61,8 @@ def measured_traffic(workload: str):
 
 
 def ops_per_attempt(scheme: int, cell: int, accept: bool) -> float:
-    """Algorithmic 32-bit VALU issue slots one update attempt needs (the design doc,
-    "ALU roofline"): its share of a Philox4x32-10 block (100 slots: 10 rounds
+    """Algorithmic 32-bit VALU issue slots one update attempt needs (the ALU
+    roofline of the step kernel): its share of a Philox4x32-10 block (100 slots: 10 rounds
     of two quarter-rate 32x32->64 multiplies and two 3-input XORs) for an
     F-bit field, plus field extraction (1), site selection (4 for a fixed
     cell grid, 8 with the per-round cell shift), word/bit addressing (5),
