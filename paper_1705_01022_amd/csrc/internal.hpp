@@ -283,7 +283,7 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
     a.NR = ws.NR;
     a.PY = ws.PY;
     a.shared_edges = ws.shared_edges;
-    a.flip_table = (pd == 1.0 ? 1u << kPatternMin : 0u) | (qr == 1.0 ? 1u << kPatternMax : 0u);
+    a.flip_table = (pd == 1.0 ? kFlipMin : 0u) | (qr == 1.0 ? kFlipMax : 0u);
     a.P_hi = (uint32_t)(ls.P >> 32);
     a.P_lo = (uint32_t)ls.P;
     a.Q_hi = (uint32_t)(ls.Q >> 32);

@@ -76,7 +76,7 @@ struct StepArgs {
     uint32_t NR;                // window rows (4 NB)
     uint32_t PY;                // LDS sy plane: column pitch in words (odd, > NR)
     uint32_t shared_edges;      // Dx < 32: edge blocks may be shared with another domain
-    uint32_t flip_table;        // no acceptance draw: bit k set iff slope pattern k flips
+    uint32_t flip_table;        // no acceptance draw: kFlipMin / kFlipMax for the patterns that flip
     uint32_t P_hi, P_lo, Q_hi, Q_lo;  // acceptance thresholds on the (A+32)-bit variate
 };
 
@@ -120,17 +120,30 @@ __device__ __forceinline__ void copy_window(const StepArgs &A, uint32_t *lds, ui
     }
 }
 
-// Slope pattern of an attempt: bit 0 sx(x,y), bit 1 sx(x+1,y), bit 2 sy(x,y),
-// bit 3 sy(x,y+1).  Local minimum (0,1,0,1) = 0xA, local maximum = 0x5.
-constexpr uint32_t kPatternMin = 0xAu, kPatternMax = 0x5u;
+// Slope pattern of an attempt: bit 0 sy(x,y+1), bit 1 sy(x,y), bit 2 sx(x,y),
+// bit 3 sx(x+1,y).  Local minimum (sx(x), sx(x+1), sy(x), sy(y+1)) = (0,1,0,1)
+// is 0x9, local maximum (1,0,1,0) is 0x6.  A flip mask holds bit k for
+// pattern k twice, at k and k + 16, so that a pattern index with garbage in
+// bit 4 selects the same bit (the bit-field extract reads 5 offset bits).
+constexpr uint32_t kPatternMin = 0x9u, kPatternMax = 0x6u;
+constexpr uint32_t kFlipMin = (1u << kPatternMin) | (1u << (kPatternMin + 16u));
+constexpr uint32_t kFlipMax = (1u << kPatternMax) | (1u << (kPatternMax + 16u));
+
+// a * b + c for a, b below 2^24 (one full-rate multiply-add); b uniform.
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
 
 // One cell's attempt in one round, decoded from its lane draw.
 struct Draw {
     uint32_t ix;    // byte offset of the site's sx-plane word: 4 (row * P + column / 32)
     uint32_t iy;    // byte offset of its sy-plane word: 4 (sy_base + (column / 32) * PY + row)
     uint32_t sh;    // site bit in those words (column % 32)
-    uint32_t mask;  // flip mask: bit kPatternMin set iff a local minimum here
-                    // deposits, bit kPatternMax iff a local maximum is removed
+    uint32_t mask;  // flip mask: kFlipMin set iff a local minimum here
+                    // deposits, kFlipMax iff a local maximum is removed
     uint32_t pos;   // domain-local u | v << 16
     uint32_t rim;   // bit 0: right column of its cell, bit 1: bottom row (DB)
 };
@@ -208,8 +221,16 @@ __device__ __forceinline__ Draw decode(const StepArgs &A, uint32_t field, uint32
     }
     const uint32_t lx = u + offx, ly = v + offy;
     Draw d;
-    d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
-    d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
+    if (SCHEME == kDB) {
+        d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
+        d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
+    } else {
+        // the same addresses with both multiply-adds in one instruction each
+        // (faster for DT and DTr; the DB kernels measured slower with them)
+        const uint32_t hx = lx >> 5;  // the site's word column
+        d.ix = mad24(ly, A.P << 2, hx << 2);
+        d.iy = mad24(hx, A.PY << 2, (A.NR * A.P + ly) << 2);
+    }
     d.sh = lx & 31u;
     d.mask = ACCEPT ? field >> A.s_bits : A.flip_table;  // acceptance prefix until accept_draws()
     d.pos = SCHEME == kDB ? u | (v << 16) : 0u;
@@ -265,14 +286,14 @@ __device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[
     uint32_t mask[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
-        mask[j] = (pre[j] < A.P_hi ? 1u << kPatternMin : 0u) | (pre[j] < A.Q_hi ? 1u << kPatternMax : 0u);
+        mask[j] = (pre[j] < A.P_hi ? kFlipMin : 0u) | (pre[j] < A.Q_hi ? kFlipMax : 0u);
     if (__ballot(any)) {
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
             if (tie[j]) {
                 const uint32_t r = philox4x32_10(A.key0, A.key1, rho, cell[j] | 0x80000000u, tile, A.c3).x;
-                if (pre[j] == A.P_hi && r < A.P_lo) mask[j] |= 1u << kPatternMin;
-                if (pre[j] == A.Q_hi && r < A.Q_lo) mask[j] |= 1u << kPatternMax;
+                if (pre[j] == A.P_hi && r < A.P_lo) mask[j] |= kFlipMin;
+                if (pre[j] == A.Q_hi && r < A.Q_lo) mask[j] |= kFlipMax;
             }
     }
 #pragma unroll
@@ -296,8 +317,9 @@ __device__ __forceinline__ Draw expand(const StepArgs &A, const CDraw &c, uint32
 
 // One update attempt (Sec. 2.1 rule) at the site of d.  With the window as
 // bit planes, a = sx(x,y) and b = sx(x+1,y) are two adjacent bits of the sx
-// row (a funnel shift over the word and the next one), c = sy(x,y) and
-// d = sy(x,y+1) the same bit of two consecutive sy rows.  A local minimum
+// row (a funnel shift over the word and the next one, which leaves further
+// bits above them: they reach bit 4 of the pattern index only), c = sy(x,y)
+// and d = sy(x,y+1) the same bit of two consecutive sy rows.  A local minimum
 // (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed (as the
 // draw's flip mask says); both flip the same four bits with LDS atomic XORs
 // (zero masks when nothing flips, or when `enable` is false), because attempts
@@ -311,8 +333,9 @@ __device__ __forceinline__ void attempt(uint32_t *lds, const Draw &d, bool enabl
     uint32_t *py = reinterpret_cast<uint32_t *>(base + d.iy);
     const uint32_t w0 = px[0], w1 = px[1];
     const uint32_t y0 = py[0], y1 = py[1];
-    const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, d.sh) & 3u;
-    const uint32_t key = ab | (__builtin_amdgcn_ubfe(y0, d.sh, 1) << 2) | (__builtin_amdgcn_ubfe(y1, d.sh, 1) << 3);
+    const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, d.sh);
+    const uint32_t cd = (__builtin_amdgcn_ubfe(y0, d.sh, 1) << 1) | __builtin_amdgcn_ubfe(y1, d.sh, 1);
+    const uint32_t key = (ab << 2) | cd;
     const uint32_t flip = __builtin_amdgcn_ubfe(d.mask, key, 1) & (enable ? 1u : 0u);
     const uint32_t m = flip << d.sh;
     atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
