@@ -321,11 +321,11 @@ __device__ __forceinline__ Draw expand(const StepArgs &A, const CDraw &c, uint32
 // bits above them: they reach bit 4 of the pattern index only), c = sy(x,y)
 // and d = sy(x,y+1) the same bit of two consecutive sy rows.  A local minimum
 // (0,1,0,1) may deposit, a local maximum (1,0,1,0) may be removed (as the
-// draw's flip mask says); both flip the same four bits with LDS atomic XORs
-// (zero masks when nothing flips, or when `enable` is false), because attempts
-// of different cells may share a word (never a bit).  All decisions are
-// bitwise; the only branch guards the rare flip of sx(x+1) in the next word (x
-// at bit 31).
+// draw's flip mask says); both flip the same four bits with LDS atomic XORs,
+// because attempts of different cells may share a word (never a bit).  All
+// decisions are bitwise; lanes that flip nothing (or whose `enable` is false)
+// skip the XORs, and the flip of sx(x+1) in the next word (x at bit 31) is a
+// further branch.
 __device__ __forceinline__ void attempt(uint32_t *lds, const Draw &d, bool enable = true)
 {
     char *base = reinterpret_cast<char *>(lds);
@@ -338,10 +338,15 @@ __device__ __forceinline__ void attempt(uint32_t *lds, const Draw &d, bool enabl
     const uint32_t key = (ab << 2) | cd;
     const uint32_t flip = __builtin_amdgcn_ubfe(d.mask, key, 1) & (enable ? 1u : 0u);
     const uint32_t m = flip << d.sh;
-    atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
-    atomicXor(&py[0], m);             // sy(x, y)
-    atomicXor(&py[1], m);             // sy(x, y+1)
-    if (m >> 31) atomicXor(&px[1], 1u);  // sx(x+1) in the next word
+    // Most attempts flip nothing: their lanes sit out the atomics, which
+    // leaves fewer active lanes to conflict on the LDS banks (the LDS pipe,
+    // not the ALU, is what these kernels wait for).
+    if (m) {
+        atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
+        atomicXor(&py[0], m);             // sy(x, y)
+        atomicXor(&py[1], m);             // sy(x, y+1)
+        if (m >> 31) atomicXor(&px[1], 1u);  // sx(x+1) in the next word
+    }
 }
 
 // A cell's published-site slot: cell c of thread c / CPT is stored at
