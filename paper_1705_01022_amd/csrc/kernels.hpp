@@ -42,7 +42,7 @@ static __global__ void philox_kernel(uint32_t k0, uint32_t k1, const uint32_t *_
 {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const u32x4 r = philox4x32_10(k0, k1, ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    const u32x4 r = philox4x32_10_lane(k0, k1, ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
     out[4 * i] = r.x;
     out[4 * i + 1] = r.y;
     out[4 * i + 2] = r.z;
@@ -158,7 +158,7 @@ __device__ __forceinline__ uint32_t next_field(const StepArgs &A, uint32_t (&rw)
     const uint32_t per_call_mask = (128u >> A.F_log2) - 1u;
     const uint32_t F = 1u << A.F_log2;
     if ((rho & per_call_mask) == 0u) {
-        const u32x4 r = philox4x32_10(A.key0, A.key1, rho >> (7u - A.F_log2), cell, tile, A.c3);
+        const u32x4 r = philox4x32_10_lane(A.key0, A.key1, rho >> (7u - A.F_log2), cell, tile, A.c3);
         rw[0] = r.x; rw[1] = r.y; rw[2] = r.z; rw[3] = r.w;
     }
     // field f of the current word: bits F*f .. F*f+F-1 (the offset is uniform;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void accept_draws(const StepArgs &A, uint32_t (&pre)[
 #pragma unroll
         for (int j = 0; j < CPT; ++j)
             if (tie[j]) {
-                const uint32_t r = philox4x32_10(A.key0, A.key1, rho, cell[j] | 0x80000000u, tile, A.c3).x;
+                const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, cell[j] | 0x80000000u, tile, A.c3).x;
                 if (pre[j] == A.P_hi && r < A.P_lo) mask[j] |= kFlipMin;
                 if (pre[j] == A.Q_hi && r < A.Q_lo) mask[j] |= kFlipMax;
             }
@@ -826,7 +826,7 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
         constexpr int RPB = 128 >> FL;  // rounds per Philox block
         uint32_t w0[4];                 // the top cell's current block
         {
-            const u32x4 r = philox4x32_10(A.key0, A.key1, 0u, cell[0], tile, A.c3);
+            const u32x4 r = philox4x32_10_lane(A.key0, A.key1, 0u, cell[0], tile, A.c3);
             w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
         }
         draw_top0(block_field<FL>(w0, 0));
@@ -835,7 +835,7 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
             uint32_t w[CPT][4];
 #pragma unroll
             for (int j = 1; j < CPT; ++j) {
-                const u32x4 r = philox4x32_10(A.key0, A.key1, blk, cell[j], tile, A.c3);
+                const u32x4 r = philox4x32_10_lane(A.key0, A.key1, blk, cell[j], tile, A.c3);
                 w[j][0] = r.x; w[j][1] = r.y; w[j][2] = r.z; w[j][3] = r.w;
             }
 #pragma unroll
@@ -848,7 +848,7 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
                 uint32_t f16n = 0u;
                 if (k == RPB - 1) {
                     if (has_next) {
-                        const u32x4 r = philox4x32_10(A.key0, A.key1, blk + 1u, cell[0], tile, A.c3);
+                        const u32x4 r = philox4x32_10_lane(A.key0, A.key1, blk + 1u, cell[0], tile, A.c3);
                         w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
                     }
                     field[0] = block_field<FL>(w0, 0);
