@@ -336,16 +336,14 @@ __device__ __forceinline__ void attempt(uint32_t *lds, const Draw &d, bool enabl
     const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, d.sh);
     const uint32_t cd = (__builtin_amdgcn_ubfe(y0, d.sh, 1) << 1) | __builtin_amdgcn_ubfe(y1, d.sh, 1);
     const uint32_t key = (ab << 2) | cd;
-    const uint32_t flip = __builtin_amdgcn_ubfe(d.mask, key, 1) & (enable ? 1u : 0u);
-    const uint32_t m = flip << d.sh;
     // Most attempts flip nothing: their lanes sit out the atomics, which
-    // leaves fewer active lanes to conflict on the LDS banks (the LDS pipe,
-    // not the ALU, is what these kernels wait for).
-    if (m) {
+    // leaves fewer active lanes to conflict on the LDS banks.
+    if (enable && __builtin_amdgcn_ubfe(d.mask, key, 1) != 0u) {
+        const uint32_t m = 1u << d.sh;
         atomicXor(&px[0], m | (m << 1));  // sx(x), and sx(x+1) unless x is bit 31
         atomicXor(&py[0], m);             // sy(x, y)
         atomicXor(&py[1], m);             // sy(x, y+1)
-        if (m >> 31) atomicXor(&px[1], 1u);  // sx(x+1) in the next word
+        if (d.sh == 31u) atomicXor(&px[1], 1u);  // sx(x+1) in the next word
     }
 }
 
