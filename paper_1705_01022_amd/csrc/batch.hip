@@ -712,7 +712,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         S.origin_mode = (uint32_t)prm.origin_mode;
         S.n_mcs = (uint32_t)n_mcs[order[i]];
         prefix[i + 1] = prefix[i] + S.ntiles;
-        lds = std::max<size_t>(lds, step_lds_bytes(prm, nt * cpt));
+        lds = std::max<size_t>(lds, step_lds_bytes(prm, cols ? nt : nt * cpt));  // columns: one slot per lane
         attempts += (uint64_t)prm.L * prm.L * S.n_mcs;
     }
     // the kernel's own 16 bytes of static LDS come on top

@@ -55,6 +55,8 @@ int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, c
 {
     if constexpr (SCHEME == kDB && CPT >= 2) {
         if ((1u << a.log2ncx) <= 64u) {
+            // the column kernel publishes one top-cell site per lane, not one per cell
+            lds -= 8u * nt * (CPT - 1);
             // the common field widths (16 bits with acceptance draws, 8 without)
             // with whole Philox blocks per domain sweep take the unrolled variant
             constexpr int FL = ACCEPT ? 4 : 3;
