@@ -37,7 +37,7 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # they were taken on (hash of the files below).
 DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/okpz.hip",
                   "paper_1705_01022_amd/csrc/philox.hpp", "paper_1705_01022_amd/csrc/internal.hpp")
-MEASURED_TRAFFIC = {"sources": "180acfb82736d30f", "workload": "L131072",
+MEASURED_TRAFFIC = {"sources": "38af1c1e69e80ab4", "workload": "L131072",
                     "fetch_kib": 799092.0, "write_kib": 1198080.0, "fetch_scale": 2.00, "write_scale": 1.00}
 
 
