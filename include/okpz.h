@@ -406,13 +406,33 @@ int okpz_batch_snapshot(okpz_batch *batch);
 int okpz_batch_series(okpz_batch *batch, const uint64_t *times, size_t n_times, const double *p, const double *q,
                       okpz_moments *moments, okpz_correlation *corr);
 
+/* Dependency neighbourhood of a batch work item, the same function the batch
+ * kernel evaluates on the device (exposed so that it can be checked on the
+ * host).  The item is tile `tile` (row-major, L/(2 dom_x) tiles per row) of
+ * one device step of a lattice of size L with domains dom_x x dom_y (Sec. 3
+ * DTr: the step's domains are sub-tiles of the MCS's 2 dom_x x 2 dom_y
+ * tiling); new_tiling != 0 says the step is the first of an MCS with origin
+ * (ox, oy) whose previous MCS had origin (oxp, oyp) (otherwise the origins are
+ * ignored but must be < L).  out[0..3] = first tile column, number of
+ * columns, first tile row, number of rows (modulo the tiles per row / column)
+ * of the previous step's tiles the item waits for, besides its own tile:
+ * every tile of the previous step's tiling whose memory words can meet the
+ * item's.  EINVAL for invalid sizes or a tile / origin out of range.  Host
+ * only; touches no device.
+ */
+int okpz_batch_wait_set(uint32_t L, uint32_t dom_x, uint32_t dom_y, uint32_t tile, int32_t new_tiling, uint32_t ox,
+                        uint32_t oy, uint32_t oxp, uint32_t oyp, uint32_t *out);
+
 /* ------------------------------------------------------------------------
- * Serving: a request loop with continuous batching.  Requests (lattice
+ * Serving: a request loop with continuous batching (the system pattern that
+ * keeps many independent realisations of Sec. 4's studies resident at once).  Requests (lattice
  * parameters, MCS count, rates) are queued from any thread; a native worker
  * thread admits them in arrival order while their device footprint fits the
  * HBM budget and a member slot is free (flat initial lattice, resident on
  * the GPU until the request retires), advances every admitted request by up
- * to chunk_mcs MCS per tick in one persistent batch launch, and retires
+ * to chunk_mcs MCS per tick -- one persistent batch launch per block scheme
+ * present among the admitted requests (a batch holds one scheme), queued
+ * back to back on the server's stream -- and retires
  * finished requests: final moments (as okpz_measure), optionally the final
  * sites, timestamps.  Requests arriving while others run join at the next
  * tick.  Each result equals running the request alone (okpz_create +

@@ -12,9 +12,9 @@
  * State convention (one byte per site, index y*L + x, x fast, periodic):
  *   bit 0 = sx[x,y] = 1  <=>  h(x,y) - h(x-1,y) = +1
  *   bit 1 = sy[x,y] = 1  <=>  h(x,y) - h(x,y-1) = +1
- * The slope "to the left neighbour" lives on the site (Sec. 3, DB scheme:
- * for each direction one slope is encoded on-site), so an update at (x,y)
- * reads and writes sx[x,y], sx[x+1,y], sy[x,y], sy[x,y+1] only.
+ * Each site stores its x and y slopes towards its left and lower neighbours
+ * (Sec. 3, DB scheme), so an update at (x,y) reads and writes sx[x,y],
+ * sx[x+1,y], sy[x,y], sy[x,y+1] only.
  *
  * Contents
  *   1. Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,

@@ -169,6 +169,9 @@ _SIGS = {
     "okpz_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
     "okpz_batch_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
     "okpz_batch_config": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
+    "okpz_batch_wait_set": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, _P]),
     "okpz_batch_run": (ctypes.c_int, [_P, _P, _P, _P]),
     "okpz_batch_sync": (ctypes.c_int, [_P]),
     "okpz_batch_observe": (ctypes.c_int, [_P, ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
@@ -308,7 +311,7 @@ class Lattice:
         _check(load().okpz_run(self._h, n_mcs, p, q), "okpz_run")
 
     def set_threads(self, threads: int):
-        """Device-step workgroup size (64, 128, 256; 0 = default); results do not change."""
+        """Device-step workgroup size in lanes (64, 128, 256 or 512; 0 = automatic); results do not change."""
         _check(load().okpz_set_threads(self._h, threads), "okpz_set_threads")
 
     def sync(self):
@@ -401,6 +404,15 @@ def _moments_dict(m) -> dict:
             "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
             "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
             "w2": m.w2, "w2_sub": m.w2_sub}
+
+
+def batch_wait_set(L, Dx, Dy, tile, new_tiling=False, ox=0, oy=0, oxp=0, oyp=0) -> tuple:
+    """Tiles of the previous device step that a batch work item waits for
+    (host-only call): (first column, columns, first row, rows)."""
+    out = (ctypes.c_uint32 * 4)()
+    _check(load().okpz_batch_wait_set(L, Dx, Dy, tile, int(bool(new_tiling)), ox, oy, oxp, oyp, out),
+           "okpz_batch_wait_set")
+    return tuple(out)
 
 
 def _corr_dict(c) -> dict:
@@ -578,13 +590,6 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
-
-
-def _moments_dict(m: Moments) -> dict:
-    return {"mcs": m.mcs, "n_even": m.n_even, "n_odd": m.n_odd,
-            "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
-            "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
-            "w2": m.w2, "w2_sub": m.w2_sub}
 
 
 class Server:

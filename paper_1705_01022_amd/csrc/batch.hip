@@ -32,6 +32,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "neighbourhood.hpp"
 
 using namespace okpz;
 using namespace okpz_host;
@@ -144,44 +145,21 @@ batch_kernel(BatchArgs B)
                     r = lo;
                     t = off - B.tile_prefix[r];
                     if (g > 0u) {
-                        // The tiles of generation g - 1 whose memory footprint can
-                        // share a word with this item's: a tile's items touch the
-                        // words of its 2D x 2D sites plus the +1 halo, widened to
-                        // whole 32-site words (31 sites on either side) and 4-row
-                        // bands (3 rows), so tiles further than 1 + 31/Dx columns or
-                        // 1 + 3/Dy rows apart never share a word.  First step of an
-                        // MCS (new random origin): around the previous tiling's tile
-                        // holding this tile's corner, one more tile on the far side.
+                        // the tiles of generation g - 1 whose words this item can share
                         const BatchSlot &S = B.slots[r];
-                        const uint32_t lx = S.a.log2ntx, ntx = 1u << lx, nty = S.ntiles >> lx;
-                        uint32_t tx = t & (ntx - 1u), ty = t >> lx;
-                        const uint32_t ex = 31u / S.a.Dx, ey = 3u / S.a.Dy;
-                        uint32_t hix = 1u + ex, hiy = 1u + ey;
-                        if ((g & 3u) == 0u) {
+                        const bool new_tiling = (g & 3u) == 0u;
+                        uint32_t ox = 0, oy = 0, oxp = 0, oyp = 0;
+                        if (new_tiling) {
                             const uint64_t m = B.mcs_base[r] + (g >> 2);
-                            uint32_t ox, oy, oxp, oyp;
                             (void)mcs_origin(S, m, ox, oy);
                             (void)mcs_origin(S, m - 1u, oxp, oyp);
-                            const uint32_t sx = (uint32_t)__builtin_ctz(2u * S.a.Dx);
-                            const uint32_t sy = (uint32_t)__builtin_ctz(2u * S.a.Dy);
-                            tx = (((ox + (tx << sx)) - oxp) & S.a.L_mask) >> sx;
-                            ty = (((oy + (ty << sy)) - oyp) & S.a.L_mask) >> sy;
-                            hix += 1u;
-                            hiy += 1u;
                         }
-                        // columns tx - 1 - ex .. tx + hix (all of them when that wraps)
-                        cx0 = (tx + ntx - ((1u + ex) & (ntx - 1u))) & (ntx - 1u);
-                        ncol = 2u + ex + hix;
-                        cy0 = (ty + nty - ((1u + ey) & (nty - 1u))) & (nty - 1u);
-                        nrow = 2u + ey + hiy;
-                        if (ncol >= ntx) {
-                            cx0 = 0u;
-                            ncol = ntx;
-                        }
-                        if (nrow >= nty) {
-                            cy0 = 0u;
-                            nrow = nty;
-                        }
+                        const WaitSet ws = wait_set(S.a.Dx, S.a.Dy, S.a.L_mask, S.a.log2ntx, S.ntiles, t,
+                                                    new_tiling, ox, oy, oxp, oyp);
+                        cx0 = ws.cx0;
+                        ncol = ws.ncol;
+                        cy0 = ws.cy0;
+                        nrow = ws.nrow;
                     }
                 }
                 cmd[0] = r;
@@ -642,6 +620,22 @@ int okpz_batch_size(const okpz_batch *b, uint32_t *nslots)
 {
     if (!b || !nslots) return OKPZ_EINVAL;
     *nslots = (uint32_t)b->slots.size();
+    return OKPZ_OK;
+}
+
+int okpz_batch_wait_set(uint32_t L, uint32_t dom_x, uint32_t dom_y, uint32_t tile, int32_t new_tiling, uint32_t ox,
+                        uint32_t oy, uint32_t oxp, uint32_t oyp, uint32_t *out)
+{
+    if (!out || !is_pow2(L) || !is_pow2(dom_x) || !is_pow2(dom_y) || 2ull * dom_x > L || 2ull * dom_y > L)
+        return OKPZ_EINVAL;
+    const uint32_t log2ntx = ilog2(L / (2u * dom_x));
+    const uint32_t ntiles = (L / (2u * dom_x)) * (L / (2u * dom_y));
+    if (tile >= ntiles || ox >= L || oy >= L || oxp >= L || oyp >= L) return OKPZ_EINVAL;
+    const okpz::WaitSet w = okpz::wait_set(dom_x, dom_y, L - 1u, log2ntx, ntiles, tile, new_tiling != 0, ox, oy, oxp, oyp);
+    out[0] = w.cx0;
+    out[1] = w.ncol;
+    out[2] = w.cy0;
+    out[3] = w.nrow;
     return OKPZ_OK;
 }
 

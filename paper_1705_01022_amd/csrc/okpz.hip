@@ -453,15 +453,15 @@ int okpz_snapshot(okpz_lattice *lat)
 {
     if (!lat) return OKPZ_EINVAL;
     const uint32_t L = lat->prm.L;
-    if (!lat->snap) {
-        if (hipMalloc(&lat->snap, (size_t)L * L / 4) != hipSuccess) {
-            lat->snap = nullptr;
-            return OKPZ_ENOMEM;
-        }
-        if (hipMalloc(&lat->h0s, L * sizeof(int32_t)) != hipSuccess) {
-            lat->h0s = nullptr;
-            return OKPZ_ENOMEM;
-        }
+    // each buffer under its own check: a failed second allocation leaves the
+    // first in place for the next call, which then allocates only the missing one
+    if (!lat->snap && hipMalloc(&lat->snap, (size_t)L * L / 4) != hipSuccess) {
+        lat->snap = nullptr;
+        return OKPZ_ENOMEM;
+    }
+    if (!lat->h0s && hipMalloc(&lat->h0s, L * sizeof(int32_t)) != hipSuccess) {
+        lat->h0s = nullptr;
+        return OKPZ_ENOMEM;
     }
     HIP_TRY(hipMemcpyAsync(lat->snap, lat->words, (size_t)L * L / 4, hipMemcpyDeviceToDevice, lat->stream));
     const int rc = run_measure(lat, false, lat->snap, lat->h0s);

@@ -4,8 +4,10 @@
 // okpz_server_submit from any thread.  A native worker thread owns the GPU
 // work: it admits queued requests in arrival order while their HBM footprint
 // fits the budget and a member slot is free, creating a flat lattice for each
-// as a member of one batch; it then advances every member by up to `chunk`
-// MCS in one persistent batch launch (a "tick"), retires the members that
+// as a member of the batch of its block scheme (a batch holds one scheme, so
+// the worker keeps one per scheme); it then advances every member by up to
+// `chunk` MCS with one persistent launch per non-empty batch, all on the
+// server's stream (a "tick"), retires the members that
 // have finished (final moments, optional copy of the final sites, lattice
 // freed), and goes round again.  Requests arriving while others run join at
 // the next tick, so their work overlaps on the device.  Lattice state stays
@@ -37,7 +39,7 @@ struct Request {
 struct Member {
     Request req;
     okpz_lattice *lat = nullptr;
-    int32_t slot = -1;
+    int32_t slot = -1;  // slot in the batch of its block scheme
     uint64_t left = 0;
     uint64_t bytes = 0;
     double t_start = 0;
@@ -68,8 +70,8 @@ struct okpz_server {
     uint64_t submitted = 0, finished = 0;
     bool stop = false;
     int status = OKPZ_OK;  // first error of the worker
-    // worker-owned
-    okpz_batch *batch = nullptr;
+    // worker-owned: one batch per block scheme (DT, DB, DTr)
+    okpz_batch *batch[3] = {nullptr, nullptr, nullptr};
     std::vector<Member> members;
     uint64_t bytes_in_use = 0;
     okpz_server_stats stats;  // guarded by mu
@@ -99,13 +101,22 @@ void finish(okpz_server *s, Member &m, int status)
         r.status = status;
     }
     r.t_finish = s->now();
-    if (m.slot >= 0) (void)okpz_batch_remove(s->batch, m.slot);
+    if (m.slot >= 0) (void)okpz_batch_remove(s->batch[m.req.prm.block_scheme], m.slot);
     if (m.lat) (void)okpz_destroy(m.lat);
     s->bytes_in_use -= m.bytes;
     std::lock_guard<std::mutex> g(s->mu);
     s->results.push_back(r);
     s->finished += 1;
     s->cv.notify_all();
+}
+
+void drop_batches(okpz_server *s)
+{
+    for (okpz_batch *&b : s->batch)
+        if (b) {
+            (void)okpz_batch_destroy(b);
+            b = nullptr;
+        }
 }
 
 // Admit queued requests in arrival order while they fit.
@@ -130,7 +141,7 @@ void admit(okpz_server *s)
         m.t_start = s->now();
         s->bytes_in_use += m.bytes;
         int rc = okpz_create(&req.prm, s->stream, &m.lat);
-        if (rc == OKPZ_OK) rc = okpz_batch_add(s->batch, m.lat, &m.slot);
+        if (rc == OKPZ_OK) rc = okpz_batch_add(s->batch[req.prm.block_scheme], m.lat, &m.slot);
         if (rc != OKPZ_OK) {
             finish(s, m, rc);
             continue;
@@ -142,11 +153,25 @@ void admit(okpz_server *s)
     }
 }
 
+// The three per-scheme batches, configured as the server asks; on failure
+// none is left.
+int make_batches(okpz_server *s)
+{
+    int rc = OKPZ_OK;
+    for (int b = 0; b < 3 && rc == OKPZ_OK; ++b) {
+        rc = okpz_batch_create(s->stream, &s->batch[b]);
+        if (rc == OKPZ_OK)
+            rc = okpz_batch_config(s->batch[b], s->cfg.threads, s->cfg.grid, s->cfg.use_graph && s->stream);
+    }
+    if (rc != OKPZ_OK) drop_batches(s);
+    return rc;
+}
+
 void worker_main(okpz_server *s)
 {
     (void)hipSetDevice(s->device);
-    std::vector<uint64_t> n;
-    std::vector<double> p, q;
+    std::vector<uint64_t> n[3];
+    std::vector<double> p[3], q[3];
     for (;;) {
         {
             std::unique_lock<std::mutex> g(s->mu);
@@ -155,22 +180,30 @@ void worker_main(okpz_server *s)
         }
         admit(s);
         if (s->members.empty()) continue;
-        uint32_t nslots = 0;
-        (void)okpz_batch_size(s->batch, &nslots);
-        n.assign(nslots, 0);
-        p.assign(nslots, 0.0);
-        q.assign(nslots, 0.0);
+        for (int b = 0; b < 3; ++b) {
+            uint32_t nslots = 0;
+            (void)okpz_batch_size(s->batch[b], &nslots);
+            n[b].assign(nslots, 0);
+            p[b].assign(nslots, 0.0);
+            q[b].assign(nslots, 0.0);
+        }
         uint64_t attempts = 0;
         for (const Member &m : s->members) {
+            const int b = m.req.prm.block_scheme;
             const uint64_t k = std::min<uint64_t>(m.left, s->cfg.chunk_mcs);
-            n[m.slot] = k;
-            p[m.slot] = m.req.p;
-            q[m.slot] = m.req.q;
+            n[b][m.slot] = k;
+            p[b][m.slot] = m.req.p;
+            q[b][m.slot] = m.req.q;
             attempts += (uint64_t)m.req.prm.L * m.req.prm.L * k;
         }
         const double t_launch = s->now();
-        int rc = okpz_batch_run(s->batch, n.data(), p.data(), q.data());
-        if (rc == OKPZ_OK) rc = okpz_batch_sync(s->batch);
+        // one launch per scheme that has members, queued back to back on the
+        // stream, then one wait for all of them
+        int rc = OKPZ_OK;
+        for (int b = 0; b < 3 && rc == OKPZ_OK; ++b)
+            if (!n[b].empty()) rc = okpz_batch_run(s->batch[b], n[b].data(), p[b].data(), q[b].data());
+        for (int b = 0; b < 3 && rc == OKPZ_OK; ++b)  // every batch's own error flag
+            if (!n[b].empty()) rc = okpz_batch_sync(s->batch[b]);
         {
             std::lock_guard<std::mutex> g(s->mu);
             s->stats.busy_seconds += s->now() - t_launch;
@@ -178,14 +211,13 @@ void worker_main(okpz_server *s)
             if (rc == OKPZ_OK) s->stats.attempts += attempts;
         }
         if (rc != OKPZ_OK) {
-            // the batch cannot continue: fail every member and start afresh
+            // the batches cannot continue: fail every member and start afresh
             for (Member &m : s->members) finish(s, m, rc);
             s->members.clear();
-            (void)okpz_batch_destroy(s->batch);
-            s->batch = nullptr;
+            drop_batches(s);
             std::lock_guard<std::mutex> g(s->mu);
             if (s->status == OKPZ_OK) s->status = rc;
-            if (okpz_batch_create(s->stream, &s->batch) != OKPZ_OK) {
+            if (make_batches(s) != OKPZ_OK) {
                 s->stop = true;
                 s->cv.notify_all();
                 return;
@@ -224,17 +256,15 @@ int okpz_server_create(const okpz_server_config *cfg, void *hip_stream, okpz_ser
         delete s;
         return OKPZ_EHIP;
     }
-    int rc = okpz_batch_create(hip_stream, &s->batch);
-    if (rc == OKPZ_OK) rc = okpz_batch_config(s->batch, cfg->threads, cfg->grid, cfg->use_graph && hip_stream);
+    const int rc = make_batches(s);
     if (rc != OKPZ_OK) {
-        if (s->batch) okpz_batch_destroy(s->batch);
         delete s;
         return rc;
     }
     try {
         s->worker = std::thread(worker_main, s);
     } catch (...) {
-        okpz_batch_destroy(s->batch);
+        drop_batches(s);
         delete s;
         return OKPZ_ENOMEM;
     }
@@ -313,7 +343,7 @@ int okpz_server_destroy(okpz_server *s)
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    if (s->batch) okpz_batch_destroy(s->batch);
+    drop_batches(s);
     delete s;
     return OKPZ_OK;
 }
