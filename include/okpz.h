@@ -201,6 +201,34 @@ int okpz_run(okpz_lattice *lat, uint64_t n_mcs, double p, double q);
 /* Exact height moments of the current state.  Synchronous. */
 int okpz_measure(okpz_lattice *lat, okpz_moments *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid allocation): the exact
+ * height moments of okpz_measure for a packed lattice in caller-owned device
+ * memory, without a handle and without allocating anything.
+ *   dev_words   device pointer to the L*L/4-byte packed lattice (layout of
+ *               Conventions), caller-owned, read only.
+ *   L           lattice size, power of two, 64 <= L <= 2^17 (the limit of the
+ *               library's fixed 2 MiB device scratch array; larger: EINVAL).
+ *   hip_stream  stream the kernels run on (a hipStream_t; NULL = null stream).
+ *   dev_totals  device pointer, caller-owned, 8-byte aligned, 96 bytes:
+ *               receives the exact totals as 6 (lo, hi) int64 pairs of
+ *               128-bit integers: S1 even, S1 odd, S2 even, S2 odd, then two
+ *               zero pairs.
+ *   out         NULL: the call only enqueues three kernels on hip_stream and
+ *               returns (asynchronous).  Otherwise a host struct: the call
+ *               synchronises the stream and fills it as okpz_measure does,
+ *               with mcs = 0 (there is no handle to count MCS).
+ * The intermediate buffers live in the library's file-scope device array,
+ * one per device for the life of the process (its address is looked up on
+ * the first call on each device).  Every call on a device shares it: calls
+ * that overlap on one device (two streams or two threads) race; calls on one
+ * stream are ordered.  EINVAL for NULL or misaligned pointers or an L out of
+ * range (okpz_last_error says which).
+ */
+int okpz_measure_noalloc(const void *dev_words, uint32_t L, void *hip_stream, int64_t *dev_totals,
+                         okpz_moments *out);
+
 /* Store the current state as the reference time s for okpz_autocorr. */
 int okpz_snapshot(okpz_lattice *lat);
 

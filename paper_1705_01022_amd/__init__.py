@@ -139,6 +139,7 @@ _SIGS = {
     "okpz_init_from_host": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "okpz_run": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_double, ctypes.c_double]),
     "okpz_measure": (ctypes.c_int, [_P, ctypes.POINTER(Moments)]),
+    "okpz_measure_noalloc": (ctypes.c_int, [_P, ctypes.c_uint32, _P, _P, ctypes.POINTER(Moments)]),
     "okpz_snapshot": (ctypes.c_int, [_P]),
     "okpz_autocorr": (ctypes.c_int, [_P, ctypes.POINTER(Correlation)]),
     "okpz_observe": (ctypes.c_int, [_P, ctypes.POINTER(Moments), ctypes.POINTER(Correlation)]),
@@ -229,9 +230,11 @@ def _strerror(status: int) -> str:
         return "status"
 
 
-def _check(status: int, what: str):
+def _check(status: int, what: str, explained: bool = False):
+    """Raise on a failed status; the HIP error text (or, for calls that set
+    one with every error, ``explained``) goes into the message."""
     if status != OK:
-        detail = load().okpz_last_error().decode() if status == EHIP else ""
+        detail = load().okpz_last_error().decode() if (status == EHIP or explained) else ""
         raise OkpzError(status, what, detail)
 
 
@@ -404,6 +407,21 @@ def _moments_dict(m) -> dict:
             "s1_even": _to_int(m.s1_even), "s1_odd": _to_int(m.s1_odd),
             "s2_even": _to_int(m.s2_even), "s2_odd": _to_int(m.s2_odd),
             "w2": m.w2, "w2_sub": m.w2_sub}
+
+
+def measure_noalloc(dev_words: int, L: int, dev_totals: int, hip_stream: int = 0, synchronous: bool = True):
+    """Exact height moments of a packed lattice in caller-owned device memory
+    without any allocation (``okpz_measure_noalloc``).  ``dev_words``,
+    ``dev_totals`` (96 bytes, 8-byte aligned) and ``hip_stream`` are raw device
+    pointers / a raw hipStream_t.  With ``synchronous`` the call waits and
+    returns the moments (mcs = 0); otherwise it only enqueues the kernels and
+    returns None (the totals land in ``dev_totals``)."""
+    m = Moments()
+    _check(load().okpz_measure_noalloc(ctypes.c_void_p(dev_words), L,
+                                       ctypes.c_void_p(hip_stream) if hip_stream else None,
+                                       ctypes.c_void_p(dev_totals), ctypes.byref(m) if synchronous else None),
+           "okpz_measure_noalloc", explained=True)
+    return _moments_dict(m) if synchronous else None
 
 
 def batch_wait_set(L, Dx, Dy, tile, new_tiling=False, ox=0, oy=0, oxp=0, oyp=0) -> tuple:

@@ -15,7 +15,7 @@ SRC_DIR = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libokpz.so")
 ARCH = "gfx950"
-SOURCES = ["okpz.hip", "batch.hip", "server.hip"]
+SOURCES = ["okpz.hip", "batch.hip", "server.hip", "noalloc.hip"]
 
 COMPILE_FLAGS = [
     "-O3",

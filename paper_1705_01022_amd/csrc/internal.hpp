@@ -21,6 +21,8 @@ using namespace okpz;
 
 // HIP error text of the calling thread (okpz_last_error)
 int hip_fail(hipError_t e, const char *what);
+// any other status with an explanation for okpz_last_error
+int fail_with(int status, const char *what);
 
 #define HIP_TRY(expr)                                        \
     do {                                                     \
@@ -294,6 +296,9 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
 // Moments (and correlation, against the snapshot) from the 128-bit totals in
 // lat->host_out.
 void fill_moments(const okpz_lattice *lat, okpz_moments *out);
+// the same from the exact totals of the moments pass (S1 even, S1 odd, S2
+// even, S2 odd as (lo, hi) int64 pairs) of a lattice of size L at MCS mcs
+void moments_from_totals(uint64_t L, uint64_t mcs, const int64_t *totals, okpz_moments *out);
 void fill_correlation(const okpz_lattice *lat, okpz_correlation *out);
 
 }  // namespace okpz_host

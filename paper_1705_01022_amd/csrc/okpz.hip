@@ -27,6 +27,12 @@ int hip_fail(hipError_t e, const char *what)
     return OKPZ_EHIP;
 }
 
+int fail_with(int status, const char *what)
+{
+    g_last_error = what;
+    return status;
+}
+
 }  // namespace okpz_host
 
 namespace {
@@ -147,12 +153,15 @@ int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_
 
 void okpz_host::fill_moments(const okpz_lattice *lat, okpz_moments *out)
 {
-    const uint64_t L = lat->prm.L;
-    const int64_t *r = lat->host_out;
+    moments_from_totals(lat->prm.L, lat->mcs, lat->host_out, out);
+}
+
+void okpz_host::moments_from_totals(uint64_t L, uint64_t mcs, const int64_t *r, okpz_moments *out)
+{
     const __int128 s1e = pair_to_i128(r + 0), s1o = pair_to_i128(r + 2);
     const __int128 s2e = pair_to_i128(r + 4), s2o = pair_to_i128(r + 6);
     const __int128 n = (__int128)L * L, ne = n / 2, no = n / 2;
-    out->mcs = lat->mcs;
+    out->mcs = mcs;
     out->n_even = (int64_t)ne;
     out->n_odd = (int64_t)no;
     out->s1_even = to_abi(s1e);

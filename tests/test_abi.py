@@ -121,3 +121,20 @@ def test_single_hip_runtime(okpz):
     okpz.load()
     paths = okpz.hip_runtime_paths()
     assert len(paths) == 1, paths
+
+
+@pytest.mark.parametrize("words,L,totals,why", [
+    (0, 256, 4096, "null lattice pointer"),
+    (4096, 256, 0, "null totals pointer"),
+    (4096, 256, 4100, "misaligned totals pointer"),
+    (4096, 1 << 18, 4096, "L above the scratch limit"),
+    (4096, 32, 4096, "L below two blocks"),
+    (4096, 96, 4096, "L not a power of two"),
+])
+def test_measure_noalloc_rejects_before_touching_the_device(okpz, words, L, totals, why):
+    # every check runs on the host before any HIP call, so the (never
+    # dereferenced) placeholder addresses are safe without a GPU
+    with pytest.raises(okpz.OkpzError) as e:
+        okpz.measure_noalloc(words, L, totals)
+    assert e.value.status == okpz.EINVAL, why
+    assert "okpz_measure_noalloc" in str(e.value)
