@@ -1,0 +1,319 @@
+// DB device step on a row-paired LDS window (the benchmark shapes: square
+// domains of 128 or 256 sites, 8 x 8-site thread cells, at least two cells
+// per lane).  Same attempts, random draws and delayed-border order as
+// sweep_db_columns (Sec. 3 DB, Sec. 3.1 single hit); what changes is how an
+// attempt finds and tests its site:
+//
+//  * Window layout.  Row r of the staged window keeps its sx words at
+//    r * 2P + k and its sy words at r * 2P + P + k (k = 0 .. NWX-1, block k of
+//    the window), so the four slope words an attempt reads -- sx(x, y),
+//    sx(x+1, y), sy(x, y), sy(x, y+1) -- sit at one address plus the
+//    immediate offsets 0, 1, P and 3P words (two ds_read2 instructions, one
+//    address).  P and everything else sized by the domain are compile-time.
+//  * A site is one linear index s = ly * 64P + lx (ly, lx: window row and
+//    column): the byte address of its sx word is (s >> 3) & ~3, its bit is
+//    s mod 32 (the shift instructions read only the low five bits), and the
+//    sites to the right and below are s + 1 and s + 64P, which is all the
+//    delayed-border dependency checks compare.
+//  * Acceptance is decided after the slopes are read: only a local minimum
+//    (deposition, threshold P) or a local maximum (removal, threshold Q) is
+//    compared with its acceptance prefix, and the 32-bit tie-break draw is
+//    made only when that prefix equals the threshold's top bits -- for an
+//    attempt that can flip.  The variate and its thresholds are those of the
+//    generic kernels (U = prefix * 2^32 + r against P or Q), so the outcome
+//    of every attempt is the same; ties that cannot matter are just not
+//    drawn.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace okpz {
+
+// Compile-time geometry of a square D x D domain (LD = log2 D >= 5) with
+// C x C-site cells (LC = log2 C): the same window as window_shape() on the
+// host (NWX blocks, NB bands, odd sx pitch P).
+template <int LD, int LC>
+struct RowPairShape {
+    static constexpr uint32_t D = 1u << LD;
+    static constexpr uint32_t C = 1u << LC;
+    static constexpr uint32_t NWX = D / 32 + 1;
+    static constexpr uint32_t P = (NWX + 1) | 1u;
+    static constexpr uint32_t NB = D / 4 + 1;
+    static constexpr uint32_t NR = 4 * NB;
+    static constexpr uint32_t ROW = 64 * P;          // bits per window row pair (linear site index stride)
+    static constexpr uint32_t NCX = D / C;           // cells per domain row
+    static constexpr uint32_t LOG2NCX = LD - LC;
+    static constexpr uint32_t SBITS = 2 * LC;        // site-index bits of a lane draw
+    static constexpr uint32_t WORDS = NR * 2 * P;    // window words
+};
+
+// LDS words of a row-paired workgroup with nt lanes: the window, two
+// buffers of published top-cell sites, three round flags.
+template <int LD, int LC>
+__host__ __device__ constexpr uint32_t rowpair_lds_words(uint32_t nt)
+{
+    return RowPairShape<LD, LC>::WORDS + 2u * nt + 4u;
+}
+
+// Staging of the window (see copy_window) into / out of the row-paired layout.
+template <bool LOAD, uint32_t P>
+__device__ __forceinline__ void copy_window_rows(const StepArgs &A, uint32_t *lds, uint32_t bx0, uint32_t by0)
+{
+    const uint32_t nwaves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t b = wave; b < A.NB; b += nwaves) {
+        const uint64_t band = static_cast<uint64_t>((by0 + b) & A.nby_mask) << A.nbx_log2;
+        for (uint32_t t = lane; t < 8u * A.NWX; t += 64) {
+            const uint32_t k = t >> 3, wib = t & 7u, row = 4u * b + (wib & 3u);
+            const uint64_t g = ((band + ((bx0 + k) & A.nbx_mask)) << 3) + wib;
+            const uint32_t li = row * (2u * P) + (wib >> 2) * P + k;
+            if (LOAD)
+                lds[li] = A.words[g];
+            else
+                A.words[g] = lds[li];
+        }
+    }
+}
+
+// One attempt at linear site s (Sec. 2.1 rule; acceptance of Sec. 2.1's
+// rates as described above).  pre: the attempt's acceptance prefix (ACCEPT).
+// enable: false for attempts that run in a later pass.  rho, cell, tile:
+// the counters of the tie-break draw.
+// A word of the workgroup's LDS by byte address.  The row-paired kernels
+// declare no static LDS, so their dynamic LDS (the window first) starts at
+// LDS address 0 and a byte offset into it is the LDS address itself.
+using lds_word = __attribute__((address_space(3))) uint32_t;
+
+__device__ __forceinline__ lds_word *lds_at(uint32_t byte_addr)
+{
+    return reinterpret_cast<lds_word *>(static_cast<uintptr_t>(byte_addr));
+}
+
+// (a << sh) | b in one instruction (the compiler otherwise folds two such
+// terms into a three-input OR after two separate shifts).
+__device__ __forceinline__ uint32_t lshl_or(uint32_t a, uint32_t sh, uint32_t b)
+{
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(sh), "v"(b));
+    return r;
+}
+
+template <bool ACCEPT, uint32_t P>
+__device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint32_t pre, bool enable, uint32_t rho,
+                                             uint32_t cell, uint32_t tile)
+{
+    lds_word *px = lds_at((s >> 3) & ~3u);
+    const uint32_t w0 = px[0], w1 = px[1];
+    const uint32_t y0 = px[P], y1 = px[3 * P];
+    // pattern index: bit 3 sx(x+1,y), bit 2 sx(x,y), bit 1 sy(x,y), bit 0
+    // sy(x,y+1); bit 4 holds a further sx bit (the masks repeat at +16)
+    const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, s);
+    const uint32_t cd = lshl_or(__builtin_amdgcn_ubfe(y0, s, 1), 1, __builtin_amdgcn_ubfe(y1, s, 1));
+    const uint32_t key = lshl_or(ab, 2, cd);
+    bool flip;
+    if (ACCEPT) {
+        // a minimum has sy(x,y+1) = 1, a maximum 0: key bit 0 picks the
+        // threshold's top bits from pq_hi (P_hi in the high half)
+        const bool mm = enable && __builtin_amdgcn_ubfe(kFlipMin | kFlipMax, key, 1) != 0u;
+        const uint32_t thr = __builtin_amdgcn_ubfe(A.pq_hi, key << 4, 16);
+        flip = mm && pre < thr;
+        if (mm && pre == thr) {  // the prefix ties: the low 32 bits of the variate decide
+            const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
+            flip = r < ((key & 1u) ? A.P_lo : A.Q_lo);
+        }
+    } else {
+        flip = enable && __builtin_amdgcn_ubfe(A.flip_table, key, 1) != 0u;
+    }
+    if (flip) {
+        const uint32_t m1 = 1u << (s & 31u), m3 = m1 | (m1 << 1);
+        __hip_atomic_fetch_xor(&px[0], m3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);      // sx(x), sx(x+1)
+        __hip_atomic_fetch_xor(&px[P], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);      // sy(x, y)
+        __hip_atomic_fetch_xor(&px[3 * P], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // sy(x, y+1)
+        if ((int32_t)m1 < 0)  // x is bit 31: sx(x+1) is bit 0 of the next word
+            __hip_atomic_fetch_xor(&px[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Linear site of a DB lane draw: site (du, dv) = (field mod C, field / C mod
+// C) of the cell whose corner, with the round's cell-grid shift, is
+// (cu, cv) -- both wrap around the domain (Sec. 3.1 DB: the shifted cell grid
+// is periodic on the domain); origin = the window index of domain site (0,0).
+template <int LD, int LC>
+__device__ __forceinline__ uint32_t site_rows(uint32_t field, uint32_t cu, uint32_t cv, uint32_t origin)
+{
+    using S = RowPairShape<LD, LC>;
+    const uint32_t du = field & (S::C - 1u);
+    const uint32_t dv = (field >> LC) & (S::C - 1u);
+    const uint32_t u = (du + cu) & (S::D - 1u);
+    const uint32_t v = (dv + cv) & (S::D - 1u);
+    return __umul24(v, S::ROW) + u + origin;
+}
+
+// DB device step with each lane holding a column of CPT vertically stacked
+// cells (lane t: cells (t mod NCX, CPT (t / NCX) + j), j = 0 .. CPT-1, j = 0
+// on top), as in sweep_db_columns: the top cell is drawn one round ahead
+// and its site published for the column above; the cell below is read from
+// the same lane (the bottom cell: the published top cell of the column
+// below), the cell to the right from the neighbouring lane by a cross-lane
+// permute; deferred attempts run in their own wave after the first pass
+// (edges, then corners) unless they are remote (bottom row of a bottom cell
+// whose column below is in another wave), which run after the barrier.  The
+// lane-draw fields are 2^FL bits, the rounds of one Philox block unrolled.
+template <bool ACCEPT, int CPT, int LD, int LC>
+__device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem, uint32_t tile)
+{
+    using S = RowPairShape<LD, LC>;
+    constexpr int FL = ACCEPT ? 4 : 3;  // 16-bit fields with acceptance prefixes, 8-bit without
+    constexpr uint32_t F = 1u << FL;
+    constexpr int RPB = 128 >> FL;      // rounds per Philox block
+    constexpr uint32_t P = S::P;
+    constexpr uint32_t CM = S::C - 1u;
+    static_assert(S::SBITS + (ACCEPT ? 8 : 0) <= F, "field too narrow");
+    static_assert(CPT >= 2 && S::NCX <= 64, "a wave must hold whole rows of lanes");
+    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    uint32_t *lds = smem;                     // window (row-paired)
+    uint32_t *cpos = smem + S::WORDS;         // 2 x NT published top-cell sites
+    uint32_t *flags = cpos + 2u * NT;         // 3 round flags
+
+    const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
+    const uint32_t X0 = (A.ox + 2u * S::D * tx + A.set_a * S::D) & A.L_mask;
+    const uint32_t Y0 = (A.oy + 2u * S::D * ty + A.set_b * S::D) & A.L_mask;
+    const uint32_t origin = (Y0 & 3u) * S::ROW + (X0 & 31u);  // window index of domain site (0, 0)
+
+    copy_window_rows<true, P>(A, lds, X0 >> 5, Y0 >> 2);
+
+    const uint32_t cx = tid & (S::NCX - 1u), grp = tid >> S::LOG2NCX;
+    const uint32_t below_lane = (tid + S::NCX) & (NT - 1u);  // lane holding the column below
+    const bool border = (below_lane >> 6) != (tid >> 6);     // ... in another wave
+    const int rsrc = (int)((cx == S::NCX - 1u ? tid + 1u - S::NCX : tid + 1u) & 63u) << 2;  // column to the right
+    const uint32_t base_u = cx << LC;
+    const uint32_t base_v0 = (grp * CPT) << LC;               // top cell's corner row
+    const uint32_t cell0 = (grp * CPT) * S::NCX + cx;         // top cell's id; cell j = cell0 + j NCX
+
+    // field k of a Philox block, lowest bits first
+    auto field_of = [](const uint32_t(&w)[4], int k) -> uint32_t {
+        constexpr int FPW = 32 / F;
+        return (w[k / FPW] >> (F * (k % FPW))) & ((1u << F) - 1u);
+    };
+    // the round's cell-grid shift from its block field
+    auto shx_of = [](uint32_t f16) { return (f16 >> 2) & CM; };
+    auto shy_of = [](uint32_t f16) { return (f16 >> 8) & CM; };
+    // rim of an attempt from its field: bit 0 right column, bit 1 bottom row
+    auto rim_of = [](uint32_t f) {
+        return ((f & CM) == CM ? 1u : 0u) | (((f >> LC) & CM) == CM ? 2u : 0u);
+    };
+
+    BlockDraw bd = {0u, 0u, 0u, 0u};
+    uint32_t f16 = next_block_field(A, bd, 0u, tile);
+    uint32_t w0[4];  // the top cell's current Philox block
+    {
+        const u32x4 r = philox4x32_10_lane(A.key0, A.key1, 0u, cell0, tile, A.c3);
+        w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
+    }
+    uint32_t ftop = field_of(w0, 0);  // the top cell's field of the coming round
+    uint32_t stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16), base_v0 + shy_of(f16), origin);
+    cpos[tid] = stop;
+    if (tid < 3) flags[tid] = 0u;
+    __syncthreads();
+
+    const uint32_t nblk = A.rounds / RPB;
+    for (uint32_t blk = 0; blk < nblk; ++blk) {
+        uint32_t w[CPT][4];
+#pragma unroll
+        for (int j = 1; j < CPT; ++j) {
+            const u32x4 r = philox4x32_10_lane(A.key0, A.key1, blk, cell0 + j * S::NCX, tile, A.c3);
+            w[j][0] = r.x; w[j][1] = r.y; w[j][2] = r.z; w[j][3] = r.w;
+        }
+#pragma unroll
+        for (int k = 0; k < RPB; ++k) {
+            const uint32_t rho = blk * RPB + k;
+            const bool has_next = rho + 1u < A.rounds;
+            // this round's fields and sites; the top cell's was drawn last round
+            const uint32_t cu = base_u + shx_of(f16), cv = base_v0 + shy_of(f16);
+            uint32_t f[CPT], s[CPT];
+            f[0] = ftop;
+            s[0] = stop;
+#pragma unroll
+            for (int j = 1; j < CPT; ++j) {
+                f[j] = field_of(w[j], k);
+                s[j] = site_rows<LD, LC>(f[j], cu, cv + (j << LC), origin);
+            }
+            // the top cell's attempt of the next round, published for the column above
+            uint32_t f16n = 0u;
+            if (has_next) {
+                f16n = next_block_field(A, bd, rho + 1u, tile);
+                if (k == RPB - 1) {
+                    const u32x4 r = philox4x32_10_lane(A.key0, A.key1, blk + 1u, cell0, tile, A.c3);
+                    w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
+                }
+                ftop = field_of(w0, (k + 1) % RPB);
+                stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16n), base_v0 + shy_of(f16n), origin);
+                cpos[((rho + 1u) & 1u) * NT + tid] = stop;
+            }
+            // Delayed-border order dependencies (as in db_columns_round): the
+            // attempt of the cell to the right sits on the site right of mine,
+            // or the one of the cell below on the site below mine -- which
+            // defers mine only if it is in another lane or itself deferred
+            // (the first pass runs a lane's cells bottom to top).  Either
+            // places mine on its cell's right column / bottom row.
+            const uint32_t pbot = cpos[(rho & 1u) * NT + below_lane];
+            bool def[CPT];
+#pragma unroll
+            for (int j = CPT - 1; j >= 0; --j) {
+                const uint32_t pr = (uint32_t)__builtin_amdgcn_ds_bpermute(rsrc, (int)s[j]);
+                const uint32_t pd = j + 1 < CPT ? s[j + 1 < CPT ? j + 1 : j] : pbot;
+                const bool below = pd == s[j] + S::ROW && (j == CPT - 1 || def[j + 1 < CPT ? j + 1 : j]);
+                def[j] = pr == s[j] + 1u || below;
+            }
+            // remote: a deferred bottom-row attempt of a bottom cell whose column below is in another wave
+            const bool remote = border && def[CPT - 1] && (rim_of(f[CPT - 1]) & 2u);
+#pragma unroll
+            for (int j = CPT - 1; j >= 0; --j)
+                attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, !def[j], rho, cell0 + j * S::NCX, tile);
+            wave_order();
+            bool cor[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {  // deferred edges of this wave
+                cor[j] = false;
+                if (def[j] && !(j == CPT - 1 && remote)) {
+                    cor[j] = rim_of(f[j]) == 3u;
+                    if (!cor[j])
+                        attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+                }
+            }
+            wave_order();
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
+                if (cor[j])
+                    attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+            const uint64_t wave_any = __ballot(remote);  // every lane takes part in the ballot
+            if ((tid & 63u) == 0u && wave_any) atomicOr(&flags[rho % 3u], 1u);
+            if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
+            __syncthreads();
+            if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
+                const bool rc = remote && rim_of(f[CPT - 1]) == 3u;
+                if (remote && !rc)
+                    attempt_rows<ACCEPT, P>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
+                                            cell0 + (CPT - 1) * S::NCX, tile);
+                wave_order();
+                if (rc)
+                    attempt_rows<ACCEPT, P>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
+                                            cell0 + (CPT - 1) * S::NCX, tile);
+                __syncthreads();
+            }
+            f16 = f16n;
+        }
+    }
+    copy_window_rows<false, P>(A, lds, X0 >> 5, Y0 >> 2);
+}
+
+// The device-step kernel on the row-paired window.  Without acceptance
+// draws it is held to six waves per SIMD.
+template <bool ACCEPT, int CPT, int LD, int LC>
+__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(ACCEPT ? 1 : 6)))
+step_db_rows_kernel(StepArgs A)
+{
+    extern __shared__ uint32_t smem[];
+    sweep_db_rows<ACCEPT, CPT, LD, LC>(A, smem, blockIdx.x);
+}
+
+}  // namespace okpz

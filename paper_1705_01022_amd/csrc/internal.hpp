@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/okpz.h"
+#include "db_rows.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
 
@@ -290,6 +291,7 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
     a.P_lo = (uint32_t)ls.P;
     a.Q_hi = (uint32_t)(ls.Q >> 32);
     a.Q_lo = (uint32_t)ls.Q;
+    a.pq_hi = (a.P_hi | a.Q_hi) < 0x10000u ? (a.Q_hi | (a.P_hi << 16)) : 0u;
     return a;
 }
 

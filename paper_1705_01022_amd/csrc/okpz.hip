@@ -54,12 +54,40 @@ int launch_instance(Kernel *fn, uint32_t nt, uint32_t ntiles, size_t lds, hipStr
     return OKPZ_OK;
 }
 
-// DB with at least two cells per lane and at most 64 cells per domain row
-// runs the column-mapped kernel (same results, less bookkeeping).
+// The row-paired DB kernel for its shapes: square 128- or 256-site domains
+// of 8 x 8-site cells (lane draws of 6 site bits in 16-bit fields with
+// acceptance prefixes, 8-bit without), two or four cells per lane.
+template <bool ACCEPT, int CPT>
+bool launch_db_rows(uint32_t nt, uint32_t ntiles, hipStream_t st, const StepArgs &a, int &rc)
+{
+    if constexpr (CPT == 2 || CPT == 4) {
+        constexpr uint32_t FL = ACCEPT ? 4u : 3u;
+        if (a.Dx != a.Dy || a.log2Cx != 3u || a.log2Cy != 3u || a.s_bits != 6u || a.F_log2 != FL ||
+            a.shared_edges)
+            return false;
+        if (a.Dx == 256u) {
+            rc = launch_instance(&step_db_rows_kernel<ACCEPT, CPT, 8, 3>, nt, ntiles,
+                                 4u * rowpair_lds_words<8, 3>(nt), st, a);
+            return true;
+        }
+        if (a.Dx == 128u) {
+            rc = launch_instance(&step_db_rows_kernel<ACCEPT, CPT, 7, 3>, nt, ntiles,
+                                 4u * rowpair_lds_words<7, 3>(nt), st, a);
+            return true;
+        }
+    }
+    return false;
+}
+
+// DB runs the row-paired kernel where it applies, else, with at least two
+// cells per lane and at most 64 cells per domain row, the column-mapped
+// kernel (same results, less bookkeeping than the generic one).
 template <int SCHEME, bool ACCEPT, int CPT>
 int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
     if constexpr (SCHEME == kDB && CPT >= 2) {
+        int rc = OKPZ_OK;
+        if (launch_db_rows<ACCEPT, CPT>(nt, ntiles, st, a, rc)) return rc;
         if ((1u << a.log2ncx) <= 64u) {
             // the column kernel publishes one top-cell site per lane, not one per cell
             lds -= 8u * nt * (CPT - 1);
