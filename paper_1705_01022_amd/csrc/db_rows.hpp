@@ -5,15 +5,16 @@
 // attempt finds and tests its site:
 //
 //  * Window layout.  Row r of the staged window keeps its sx words at
-//    r * 2P + k and its sy words at r * 2P + P + k (k = 0 .. NWX-1, block k of
-//    the window), so the four slope words an attempt reads -- sx(x, y),
-//    sx(x+1, y), sy(x, y), sy(x, y+1) -- sit at one address plus the
-//    immediate offsets 0, 1, P and 3P words (two ds_read2 instructions, one
-//    address).  P and everything else sized by the domain are compile-time.
-//  * A site is one linear index s = ly * 64P + lx (ly, lx: window row and
+//    r * W + k and its sy words at r * W + P + k (k = 0 .. NWX-1, block k of
+//    the window; row pitch W = 2P + 1 words), so the four slope words an
+//    attempt reads -- sx(x, y), sx(x+1, y), sy(x, y), sy(x, y+1) -- sit at
+//    one address plus the immediate offsets 0, 1, P and P + W words (two
+//    ds_read2 instructions, one address).  P, W and everything else sized by
+//    the domain are compile-time.
+//  * A site is one linear index s = ly * 32W + lx (ly, lx: window row and
 //    column): the byte address of its sx word is (s >> 3) & ~3, its bit is
 //    s mod 32 (the shift instructions read only the low five bits), and the
-//    sites to the right and below are s + 1 and s + 64P, which is all the
+//    sites to the right and below are s + 1 and s + 32W, which is all the
 //    delayed-border dependency checks compare.
 //  * Acceptance is decided after the slopes are read: only a local minimum
 //    (deposition, threshold P) or a local maximum (removal, threshold Q) is
@@ -40,11 +41,14 @@ struct RowPairShape {
     static constexpr uint32_t P = (NWX + 1) | 1u;
     static constexpr uint32_t NB = D / 4 + 1;
     static constexpr uint32_t NR = 4 * NB;
-    static constexpr uint32_t ROW = 64 * P;          // bits per window row pair (linear site index stride)
+    // words per window row (sx words, sy words, one pad word): odd, so that
+    // rows 32 apart -- the two lane rows of a wave -- fall on different banks
+    static constexpr uint32_t PITCH = 2 * P + 1;
+    static constexpr uint32_t ROW = 32 * PITCH;      // bits per window row (linear site index stride)
     static constexpr uint32_t NCX = D / C;           // cells per domain row
     static constexpr uint32_t LOG2NCX = LD - LC;
     static constexpr uint32_t SBITS = 2 * LC;        // site-index bits of a lane draw
-    static constexpr uint32_t WORDS = NR * 2 * P;    // window words
+    static constexpr uint32_t WORDS = NR * PITCH;    // window words
 };
 
 // LDS words of a row-paired workgroup with nt lanes: the window, two
@@ -56,7 +60,7 @@ __host__ __device__ constexpr uint32_t rowpair_lds_words(uint32_t nt)
 }
 
 // Staging of the window (see copy_window) into / out of the row-paired layout.
-template <bool LOAD, uint32_t P>
+template <bool LOAD, uint32_t P, uint32_t PITCH>
 __device__ __forceinline__ void copy_window_rows(const StepArgs &A, uint32_t *lds, uint32_t bx0, uint32_t by0)
 {
     const uint32_t nwaves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -65,7 +69,7 @@ __device__ __forceinline__ void copy_window_rows(const StepArgs &A, uint32_t *ld
         for (uint32_t t = lane; t < 8u * A.NWX; t += 64) {
             const uint32_t k = t >> 3, wib = t & 7u, row = 4u * b + (wib & 3u);
             const uint64_t g = ((band + ((bx0 + k) & A.nbx_mask)) << 3) + wib;
-            const uint32_t li = row * (2u * P) + (wib >> 2) * P + k;
+            const uint32_t li = row * PITCH + (wib >> 2) * P + k;
             if (LOAD)
                 lds[li] = A.words[g];
             else
@@ -97,38 +101,57 @@ __device__ __forceinline__ uint32_t lshl_or(uint32_t a, uint32_t sh, uint32_t b)
     return r;
 }
 
-template <bool ACCEPT, uint32_t P>
+// a * b + c with a, b 24-bit signed (b uniform), as one instruction
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// 1 << (s mod 32) and 3 << (s mod 32), the flip masks of sx(x) and of
+// sx(x), sx(x+1) (shift instructions read the low five bits of s); written
+// as instructions so that the test for x = bit 31 stays one compare.
+__device__ __forceinline__ void flip_masks(uint32_t s, uint32_t &m1, uint32_t &m3)
+{
+    asm("v_lshlrev_b32 %0, %1, 1" : "=v"(m1) : "v"(s));
+    asm("v_lshlrev_b32 %0, %1, 3" : "=v"(m3) : "v"(s));
+}
+
+template <bool ACCEPT, uint32_t P, uint32_t PITCH>
 __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint32_t pre, bool enable, uint32_t rho,
                                              uint32_t cell, uint32_t tile)
 {
     lds_word *px = lds_at((s >> 3) & ~3u);
     const uint32_t w0 = px[0], w1 = px[1];
-    const uint32_t y0 = px[P], y1 = px[3 * P];
+    const uint32_t y0 = px[P], y1 = px[P + PITCH];
     // pattern index: bit 3 sx(x+1,y), bit 2 sx(x,y), bit 1 sy(x,y), bit 0
     // sy(x,y+1); bit 4 holds a further sx bit (the masks repeat at +16)
     const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, s);
-    const uint32_t cd = lshl_or(__builtin_amdgcn_ubfe(y0, s, 1), 1, __builtin_amdgcn_ubfe(y1, s, 1));
-    const uint32_t key = lshl_or(ab, 2, cd);
+    const uint32_t d = __builtin_amdgcn_ubfe(y1, s, 1);
+    const uint32_t key = lshl_or(ab, 2, lshl_or(__builtin_amdgcn_ubfe(y0, s, 1), 1, d));
     bool flip;
     if (ACCEPT) {
-        // a minimum has sy(x,y+1) = 1, a maximum 0: key bit 0 picks the
-        // threshold's top bits from pq_hi (P_hi in the high half)
+        // a minimum has sy(x,y+1) = 1, a maximum 0: the prefix is compared
+        // with P_hi when d = 1, with Q_hi when d = 0, i.e. pre - d (P_hi - Q_hi)
+        // with Q_hi (signed: the shifted prefix can be negative)
         const bool mm = enable && __builtin_amdgcn_ubfe(kFlipMin | kFlipMax, key, 1) != 0u;
-        const uint32_t thr = __builtin_amdgcn_ubfe(A.pq_hi, key << 4, 16);
-        flip = mm && pre < thr;
-        if (mm && pre == thr) {  // the prefix ties: the low 32 bits of the variate decide
+        const int rel = mad_i24((int)d, -A.pq_delta, (int)pre);
+        flip = mm && rel < (int)A.Q_hi;
+        if (mm && rel == (int)A.Q_hi) {  // the prefix ties: the low 32 bits of the variate decide
             const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
-            flip = r < ((key & 1u) ? A.P_lo : A.Q_lo);
+            flip = r < (d ? A.P_lo : A.Q_lo);
         }
     } else {
         flip = enable && __builtin_amdgcn_ubfe(A.flip_table, key, 1) != 0u;
     }
     if (flip) {
-        const uint32_t m1 = 1u << (s & 31u), m3 = m1 | (m1 << 1);
+        uint32_t m1, m3;
+        flip_masks(s, m1, m3);
         __hip_atomic_fetch_xor(&px[0], m3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);      // sx(x), sx(x+1)
         __hip_atomic_fetch_xor(&px[P], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);      // sy(x, y)
-        __hip_atomic_fetch_xor(&px[3 * P], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // sy(x, y+1)
-        if ((int32_t)m1 < 0)  // x is bit 31: sx(x+1) is bit 0 of the next word
+        __hip_atomic_fetch_xor(&px[P + PITCH], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // sy(x, y+1)
+        if (m3 == 0x80000000u)  // x is bit 31: sx(x+1) is bit 0 of the next word
             __hip_atomic_fetch_xor(&px[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
@@ -137,14 +160,17 @@ __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint
 // C) of the cell whose corner, with the round's cell-grid shift, is
 // (cu, cv) -- both wrap around the domain (Sec. 3.1 DB: the shifted cell grid
 // is periodic on the domain); origin = the window index of domain site (0,0).
+// wrapv = false: the caller knows the row cannot pass the domain's last row
+// (only cells of the last cell row can wrap vertically).
 template <int LD, int LC>
-__device__ __forceinline__ uint32_t site_rows(uint32_t field, uint32_t cu, uint32_t cv, uint32_t origin)
+__device__ __forceinline__ uint32_t site_rows(uint32_t field, uint32_t cu, uint32_t cv, uint32_t origin,
+                                              bool wrapv)
 {
     using S = RowPairShape<LD, LC>;
     const uint32_t du = field & (S::C - 1u);
     const uint32_t dv = (field >> LC) & (S::C - 1u);
     const uint32_t u = (du + cu) & (S::D - 1u);
-    const uint32_t v = (dv + cv) & (S::D - 1u);
+    const uint32_t v = wrapv ? (dv + cv) & (S::D - 1u) : dv + cv;
     return __umul24(v, S::ROW) + u + origin;
 }
 
@@ -179,7 +205,7 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
     const uint32_t Y0 = (A.oy + 2u * S::D * ty + A.set_b * S::D) & A.L_mask;
     const uint32_t origin = (Y0 & 3u) * S::ROW + (X0 & 31u);  // window index of domain site (0, 0)
 
-    copy_window_rows<true, P>(A, lds, X0 >> 5, Y0 >> 2);
+    copy_window_rows<true, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
 
     const uint32_t cx = tid & (S::NCX - 1u), grp = tid >> S::LOG2NCX;
     const uint32_t below_lane = (tid + S::NCX) & (NT - 1u);  // lane holding the column below
@@ -197,10 +223,10 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
     // the round's cell-grid shift from its block field
     auto shx_of = [](uint32_t f16) { return (f16 >> 2) & CM; };
     auto shy_of = [](uint32_t f16) { return (f16 >> 8) & CM; };
-    // rim of an attempt from its field: bit 0 right column, bit 1 bottom row
-    auto rim_of = [](uint32_t f) {
-        return ((f & CM) == CM ? 1u : 0u) | (((f >> LC) & CM) == CM ? 2u : 0u);
-    };
+    // rim of an attempt from its field: on its cell's bottom row; on its corner
+    // (bottom row and right column: all site-index bits set)
+    auto bottom_of = [](uint32_t f) { return (f & (CM << LC)) == (CM << LC); };
+    auto corner_of = [](uint32_t f) { return (f & ((1u << S::SBITS) - 1u)) == (1u << S::SBITS) - 1u; };
 
     BlockDraw bd = {0u, 0u, 0u, 0u};
     uint32_t f16 = next_block_field(A, bd, 0u, tile);
@@ -210,7 +236,7 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
         w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
     }
     uint32_t ftop = field_of(w0, 0);  // the top cell's field of the coming round
-    uint32_t stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16), base_v0 + shy_of(f16), origin);
+    uint32_t stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16), base_v0 + shy_of(f16), origin, false);
     cpos[tid] = stop;
     if (tid < 3) flags[tid] = 0u;
     __syncthreads();
@@ -235,7 +261,8 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
 #pragma unroll
             for (int j = 1; j < CPT; ++j) {
                 f[j] = field_of(w[j], k);
-                s[j] = site_rows<LD, LC>(f[j], cu, cv + (j << LC), origin);
+                // a lane's lower cells are never in the last cell row but the bottom one
+                s[j] = site_rows<LD, LC>(f[j], cu, cv + (j << LC), origin, j == CPT - 1);
             }
             // the top cell's attempt of the next round, published for the column above
             uint32_t f16n = 0u;
@@ -246,7 +273,7 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
                     w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
                 }
                 ftop = field_of(w0, (k + 1) % RPB);
-                stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16n), base_v0 + shy_of(f16n), origin);
+                stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16n), base_v0 + shy_of(f16n), origin, false);
                 cpos[((rho + 1u) & 1u) * NT + tid] = stop;
             }
             // Delayed-border order dependencies (as in db_columns_round): the
@@ -264,52 +291,62 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
                 const bool below = pd == s[j] + S::ROW && (j == CPT - 1 || def[j + 1 < CPT ? j + 1 : j]);
                 def[j] = pr == s[j] + 1u || below;
             }
-            // remote: a deferred bottom-row attempt of a bottom cell whose column below is in another wave
-            const bool remote = border && def[CPT - 1] && (rim_of(f[CPT - 1]) & 2u);
+            // The first pass: every attempt that no other waits for, bottom to top.
 #pragma unroll
             for (int j = CPT - 1; j >= 0; --j)
-                attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, !def[j], rho, cell0 + j * S::NCX, tile);
-            wave_order();
-            bool cor[CPT];
+                attempt_rows<ACCEPT, P, S::PITCH>(A, s[j], f[j] >> S::SBITS, !def[j], rho, cell0 + j * S::NCX, tile);
+            // Deferred attempts of this wave (about one lane in a hundred
+            // holds one, so about half the waves skip the section): edges,
+            // then corners; remote ones -- a bottom-row attempt of a bottom
+            // cell whose column below is in another wave -- after the barrier.
+            bool anydef = false;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {  // deferred edges of this wave
-                cor[j] = false;
-                if (def[j] && !(j == CPT - 1 && remote)) {
-                    cor[j] = rim_of(f[j]) == 3u;
-                    if (!cor[j])
-                        attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+            for (int j = 0; j < CPT; ++j) anydef = anydef || def[j];
+            bool remote = false;
+            if (anydef) {
+                remote = border && def[CPT - 1] && bottom_of(f[CPT - 1]);
+                wave_order();
+                bool cor[CPT];
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {  // deferred edges
+                    cor[j] = false;
+                    if (def[j] && !(j == CPT - 1 && remote)) {
+                        cor[j] = corner_of(f[j]);
+                        if (!cor[j])
+                            attempt_rows<ACCEPT, P, S::PITCH>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+                    }
                 }
-            }
-            wave_order();
+                wave_order();
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)  // deferred corners of this wave
-                if (cor[j])
-                    attempt_rows<ACCEPT, P>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+                for (int j = 0; j < CPT; ++j)  // deferred corners
+                    if (cor[j])
+                        attempt_rows<ACCEPT, P, S::PITCH>(A, s[j], f[j] >> S::SBITS, true, rho, cell0 + j * S::NCX, tile);
+            }
             const uint64_t wave_any = __ballot(remote);  // every lane takes part in the ballot
             if ((tid & 63u) == 0u && wave_any) atomicOr(&flags[rho % 3u], 1u);
             if (tid == 0) flags[(rho + 1u) % 3u] = 0u;
             __syncthreads();
             if (flags[rho % 3u]) {  // remote edges, then remote corners of the same waves
-                const bool rc = remote && rim_of(f[CPT - 1]) == 3u;
+                const bool rc = remote && corner_of(f[CPT - 1]);
                 if (remote && !rc)
-                    attempt_rows<ACCEPT, P>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
+                    attempt_rows<ACCEPT, P, S::PITCH>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
                                             cell0 + (CPT - 1) * S::NCX, tile);
                 wave_order();
                 if (rc)
-                    attempt_rows<ACCEPT, P>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
+                    attempt_rows<ACCEPT, P, S::PITCH>(A, s[CPT - 1], f[CPT - 1] >> S::SBITS, true, rho,
                                             cell0 + (CPT - 1) * S::NCX, tile);
                 __syncthreads();
             }
             f16 = f16n;
         }
     }
-    copy_window_rows<false, P>(A, lds, X0 >> 5, Y0 >> 2);
+    copy_window_rows<false, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
 }
 
-// The device-step kernel on the row-paired window.  Without acceptance
-// draws it is held to six waves per SIMD.
+// The device-step kernel on the row-paired window, held to six waves per
+// SIMD (its LDS allows six 256-lane workgroups per compute unit).
 template <bool ACCEPT, int CPT, int LD, int LC>
-__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(ACCEPT ? 1 : 6)))
+__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(6)))
 step_db_rows_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];

@@ -291,7 +291,7 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
     a.P_lo = (uint32_t)ls.P;
     a.Q_hi = (uint32_t)(ls.Q >> 32);
     a.Q_lo = (uint32_t)ls.Q;
-    a.pq_hi = (a.P_hi | a.Q_hi) < 0x10000u ? (a.Q_hi | (a.P_hi << 16)) : 0u;
+    a.pq_delta = (int32_t)a.P_hi - (int32_t)a.Q_hi;
     return a;
 }
 

@@ -78,7 +78,7 @@ struct StepArgs {
     uint32_t shared_edges;      // Dx < 32: edge blocks may be shared with another domain
     uint32_t flip_table;        // no acceptance draw: kFlipMin / kFlipMax for the patterns that flip
     uint32_t P_hi, P_lo, Q_hi, Q_lo;  // acceptance thresholds on the (A+32)-bit variate
-    uint32_t pq_hi;             // Q_hi | P_hi << 16 when both fit 16 bits (row-paired DB kernel)
+    int32_t pq_delta;           // P_hi - Q_hi (row-paired DB kernel)
 };
 
 
