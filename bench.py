@@ -26,19 +26,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CUS, SIMDS_PER_CU = 256, 4
+CLOCK_GHZ = 2.4
 # VALU issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (32-bit integer lane ops)
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+VALU_PEAK_GOPS = CUS * SIMDS_PER_CU * 16 * CLOCK_GHZ
 
 
-# HBM bytes per device-step launch of the benchmark workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one counter per run), scaled by
-# what the same counters read for the 4 GiB lattice copy in the same runs
-# (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00); valid only for the device sources
-# they were taken on (hash of the files below).
-DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/okpz.hip",
-                  "paper_1705_01022_amd/csrc/philox.hpp", "paper_1705_01022_amd/csrc/internal.hpp")
-MEASURED_TRAFFIC = {"sources": "38af1c1e69e80ab4", "workload": "L131072",
-                    "fetch_kib": 799092.0, "write_kib": 1198080.0, "fetch_scale": 2.00, "write_scale": 1.00}
+# Counters of the benchmark's device-step kernel, per launch, from rocprofv3
+# runs of the commands in profiles/step_kernel_L131072_DTrDB.md (one counter
+# group per run): HBM bytes from FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch), scaled by what the same counters read for the 4 GiB lattice copy
+# in the same runs (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00), and the SQ / GRBM
+# counters behind rocprofv3's VALUBusy, LdsUtil and LDSBankConflict.  Valid
+# only for the device sources they were taken on (hash of the files below);
+# otherwise the bench reports them as null.
+DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/db_rows.hpp",
+                  "paper_1705_01022_amd/csrc/okpz.hip", "paper_1705_01022_amd/csrc/philox.hpp",
+                  "paper_1705_01022_amd/csrc/internal.hpp")
+MEASURED = {"sources": None, "workload": "L131072"}
 
 
 def device_sources_hash() -> str:
@@ -51,23 +56,54 @@ def device_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per step launch from the counters, or None if they were taken
-    on other sources or another workload."""
-    t = MEASURED_TRAFFIC
-    if workload != t["workload"] or device_sources_hash() != t["sources"]:
+def measured_counters(workload: str):
+    """The stored per-launch counters, or None if they were taken on other
+    sources or another workload."""
+    if workload != MEASURED["workload"] or device_sources_hash() != MEASURED["sources"]:
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    return MEASURED
+
+
+def counter_rates(m: dict, launch_s: float, wave_attempts: float) -> dict:
+    """Rates against the chip from stored per-launch counters (rocprofv3's
+    derived-metric definitions; CU_NUM = 256, GRBM_GUI_ACTIVE = GPU cycles of
+    the dispatch):
+      valu_busy       = SQ_ACTIVE_INST_VALU / (CU_NUM x GRBM_GUI_ACTIVE)
+                        (quad-cycles of VALU work per SIMD-quad-cycle: 1 = every
+                        SIMD issues a VALU instruction every 4 cycles)
+      lds_util        = SQ_LDS_IDX_ACTIVE / (CU_NUM x GRBM_GUI_ACTIVE)
+      lds_bank_conflict_frac = SQ_LDS_BANK_CONFLICT / (CU_NUM x GRBM_GUI_ACTIVE)
+                        (share of the LDS's cycles lost to bank conflicts)
+      lds_conflicts_per_access = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)
+      hbm_measured_frac = (FETCH x 2.00 + WRITE x 1.00) bytes / launch time / 8 TB/s
+    plus instruction counts per wave-attempt (64 update attempts)."""
+    gui = m["GRBM_GUI_ACTIVE"]
+    traffic = 1024.0 * (m["FETCH_SIZE_KiB"] * 2.00 + m["WRITE_SIZE_KiB"] * 1.00)
+    return {
+        "valu_busy": m["SQ_ACTIVE_INST_VALU"] / (CUS * gui),
+        "lds_util": m["SQ_LDS_IDX_ACTIVE"] / (CUS * gui),
+        "lds_bank_conflict_frac": m["SQ_LDS_BANK_CONFLICT"] / (CUS * gui),
+        "lds_conflicts_per_access": m["SQ_LDS_BANK_CONFLICT"] / (m["SQ_LDS_IDX_ACTIVE"] - m["SQ_LDS_BANK_CONFLICT"]),
+        "valu_insts_per_wave_attempt": m["SQ_INSTS_VALU"] / wave_attempts,
+        "salu_insts_per_wave_attempt": m["SQ_INSTS_SALU"] / wave_attempts,
+        "lds_insts_per_wave_attempt": m["SQ_INSTS_LDS"] / wave_attempts,
+        "lds_conflict_cycles_per_wave_attempt": m["SQ_LDS_BANK_CONFLICT"] / wave_attempts,
+        "traffic_bytes": traffic,
+        "hbm_measured_GBs": traffic / launch_s / 1e9,
+        "hbm_measured_frac": traffic / launch_s / 1e9 / HBM_PEAK_GBS,
+        "counter_launch_ms": m["launch_ms"],
+        "gpu_clock_GHz": gui / (m["launch_ms"] * 1e-3) / 1e9,
+    }
 
 
 def ops_per_attempt(scheme: int, cell: int, accept: bool) -> float:
-    """Algorithmic 32-bit VALU issue slots one update attempt needs (the ALU
-    roofline of the step kernel): its share of a Philox4x32-10 block (100 slots: 10 rounds
-    of two quarter-rate 32x32->64 multiplies and two 3-input XORs) for an
-    F-bit field, plus field extraction (1), site selection (4 for a fixed
-    cell grid, 8 with the per-round cell shift), word/bit addressing (5),
-    reading the four slopes (6), the decision (1, or 5 with an acceptance
-    draw) and the flip masks (3)."""
+    """A hand-counted model (kept for comparison with the measured counters):
+    32-bit VALU issue slots one update attempt needs -- its share of a
+    Philox4x32-10 block (100 slots: 10 rounds of two quarter-rate 32x32->64
+    multiplies and two 3-input XORs) for an F-bit field, plus field extraction
+    (1), site selection (4 for a fixed cell grid, 8 with the per-round cell
+    shift), word/bit addressing (5), reading the four slopes (6), the decision
+    (1, or 5 with an acceptance draw) and the flip masks (3)."""
     sites = cell * cell if scheme == 1 else cell * cell // 4
     s_bits = max(0, sites.bit_length() - 1)
     if accept:
@@ -200,6 +236,38 @@ def batched_comparison(okpz, n_batched=200, n_plain=4, tune_mcs=10):
             "observe_all_ms": {"batched": 1e3 * el_ob, "per_member": 1e3 * el_ol}}
 
 
+def config2_comparison(okpz, n_batched=100, n_plain=20):
+    """The L = 4096 workload (DTrDT, 256 x 256-site domains, TC=1,1, p=1,
+    q=0): its 64 realisations (streams 0..63, seed 1) as one batch against one
+    lattice on the plain path (okpz_run, 4 device-step launches per MCS).
+    The 4 MiB lattices are cache-resident, so only attempts/s is reported."""
+    L, D, C = 4096, 256, 8
+    b = okpz.Batch()
+    for st in range(64):
+        b.lattice(L, D, D, C, C, okpz.BLOCK_DT, seed=1, stream=st)
+    n = 64
+    b.run([2] * n, [1.0] * n, [0.0] * n)
+    b.sync()
+    t0 = time.perf_counter()
+    b.run([n_batched] * n, [1.0] * n, [0.0] * n)
+    b.sync()
+    el_b = time.perf_counter() - t0
+    b.close()
+    with okpz.Lattice(L, D, D, C, C, okpz.BLOCK_DT, seed=1, stream=0) as lat:
+        lat.run(2, 1.0, 0.0)
+        lat.sync()
+        t0 = time.perf_counter()
+        lat.run(n_plain, 1.0, 0.0)
+        lat.sync()
+        el_p = time.perf_counter() - t0
+    batched = 64 * L * L * n_batched / el_b
+    plain = L * L * n_plain / el_p
+    return {"workload": "L=4096 (4 MiB packed), DTrDT, D=256x256, TC=1,1, p=1 q=0; 64 realisations "
+                        "(streams 0..63) as one batch vs one lattice on the plain path",
+            "batched_attempts_per_s": batched, "batched_mcs": n_batched,
+            "plain_attempts_per_s": plain, "plain_mcs": n_plain, "batched_over_plain": batched / plain}
+
+
 def _serve_window(okpz, reqs, time_scale=1.0, chunk_mcs=64):
     """Replay the requests' arrival times (scaled) against a fresh server and
     return per-request latencies and the throughput of the window."""
@@ -226,7 +294,7 @@ def _serve_window(okpz, reqs, time_scale=1.0, chunk_mcs=64):
             "offered_req_per_s": 1.0 / (time_scale * (reqs[-1].arrival / len(reqs)))}
 
 
-def served_comparison(okpz, n_requests=24, plain_mcs=20):
+def served_comparison(okpz, n_requests=200, plain_mcs=20):
     """The serving workload (Poisson arrivals at 200/s, L = 2^U{9..13}, 10^3 or
     10^4 MCS, p ~ U[0.5,1], q = 1-p, DTrDB, D = min(256, L/2), TC=1,1): a
     bounded window of the first requests replayed in real time (overloaded by
@@ -270,7 +338,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the serving window")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-config2", action="store_true", help="skip the L=4096 batch-vs-plain comparison")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -323,15 +392,19 @@ def main():
     attempts_per_launch = sites / 4
     accept = not (p in (0.0, 1.0) and q in (0.0, 1.0))
     ops = ops_per_attempt(scheme, C, accept)
-    alu_achieved = attempts_per_launch * ops / step_avg_s / 1e9
-    traffic = measured_traffic(args.workload)
+    alu_model = attempts_per_launch * ops / step_avg_s / 1e9
     cells = (D // C) * (D // C)
     cpt = max(1, cells // 256)
-    if scheme == 1 and cpt >= 2 and D // C <= 64:
+    if scheme == 1 and cpt in (2, 4) and C == 8 and D in (128, 256):
+        kernel_name = "step_db_rows_kernel<accept=%s, %d cells/lane, D=%d, C=%d> (%s)" % (
+            accept, cpt, D, C, SCHEME_NAME[scheme])
+    elif scheme == 1 and cpt >= 2 and D // C <= 64:
         kernel_name = "step_db_columns_kernel<accept=%s, %d cells/lane> (%s)" % (accept, cpt, SCHEME_NAME[scheme])
     else:
         kernel_name = "step_kernel<%s, accept=%s, %d cells/lane>" % (SCHEME_NAME[scheme], accept, cpt)
     hbm_achieved = bytes_per_launch / step_avg_s / 1e9
+    ctr = measured_counters(args.workload)
+    rates = counter_rates(ctr, step_avg_s, attempts_per_launch / 64) if ctr else None
     line = {
         "metric": "site-update attempts/s",
         "value": value,
@@ -351,22 +424,28 @@ def main():
             "step": "1 MCS (L^2 attempts, 4 device-step launches) + exact W^2 and C_h(t,s) in one pass",
             "parallelism": "single GPU",
         },
+        # HBM roofline of the device-step kernel: algorithmic bytes (each
+        # launch reads and writes the active quarter of the lattice once, 0.5 B
+        # per attempt) over its mean launch time (HIP events on the lattice's
+        # stream), against 8 TB/s.  The kernel is bound by instruction issue and
+        # LDS, not by HBM: the counter-derived rates beside it say how busy
+        # those units are (valid for the sources the counters were taken on).
         "roofline": {
             "kernel": kernel_name,
-            "bound": "alu",
-            "achieved": alu_achieved,
-            "peak": VALU_PEAK_GOPS,
-            "unit": "Gop/s",
-            "frac": alu_achieved / VALU_PEAK_GOPS,
-            "traffic": traffic,
-            "traffic_unit": "B/launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+            "bound": "hbm",
+            "achieved": hbm_achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": hbm_achieved / HBM_PEAK_GBS,
+            "traffic": rates["traffic_bytes"] if rates else None,
+            "traffic_unit": "B/launch (HBM, rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
             "algorithmic_bytes_per_launch": bytes_per_launch,
-            "ops_per_attempt": ops,
             "avg_launch_ms": step_avg_s * 1e3,
             "launches": tm["step_launches"],
-            "hbm_achieved_GBs": hbm_achieved,
-            "hbm_peak_GBs": HBM_PEAK_GBS,
-            "hbm_frac": hbm_achieved / HBM_PEAK_GBS,
+            "counters": rates,
+            "alu_model": {"ops_per_attempt": ops, "achieved_Gops": alu_model, "peak_Gops": VALU_PEAK_GOPS,
+                          "alu_model_frac": alu_model / VALU_PEAK_GOPS,
+                          "note": "hand-counted op model, not a measurement"},
         },
         "kernel_attempts_per_s": attempts_per_launch / step_avg_s,
         "measure_ms_per_step": tm["measure_ms"] / max(1, args.steps),
@@ -381,6 +460,9 @@ def main():
     if not args.no_batched:
         print("bench: batched vs plain", file=sys.stderr, flush=True)
         line["batched"] = batched_comparison(okpz)
+    if not args.no_config2:
+        print("bench: L=4096 batch vs plain", file=sys.stderr, flush=True)
+        line["config2"] = config2_comparison(okpz)
     if not args.no_served:
         print("bench: serving window", file=sys.stderr, flush=True)
         line["served"] = served_comparison(okpz, args.serve_requests)

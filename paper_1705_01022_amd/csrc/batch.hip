@@ -104,12 +104,18 @@ __device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint
 // acceptance draws iff FL = 4 and a whole number of Philox blocks of rounds,
 // so the sweep with the rounds of one block unrolled serves them all.
 //
+// LD > 0 (with COLS and FL > 0): every lattice also has square 2^LD-site
+// domains of 8 x 8-site cells, so the row-paired DB sweep serves them all.
+//
 // DT and DTr with at most 4 cells per lane: six waves per SIMD (80 VGPRs and
 // 40 bytes spilled to scratch; the LDS allows seven workgroups per compute
 // unit) run the 512-realisation batch 5 % faster than the five that the
-// unconstrained 93 VGPRs allow.
-template <int SCHEME, int CPT, bool COLS, int FL>
-__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(SCHEME != kDB && CPT <= 4 ? 6 : 1)))
+// unconstrained 93 VGPRs allow.  The row-paired sweep runs two cells per
+// lane (75 VGPRs, six waves per SIMD): with four, the batch kernel's own state
+// on top of the sweep's pushes it into scratch spills.
+template <int SCHEME, int CPT, bool COLS, int FL, int LD>
+__global__ void __launch_bounds__(kMaxStepThreads)
+__attribute__((amdgpu_waves_per_eu((SCHEME != kDB && CPT <= 4) || LD > 0 ? 6 : 1)))
 batch_kernel(BatchArgs B)
 {
     extern __shared__ uint32_t smem[];
@@ -229,7 +235,9 @@ batch_kernel(BatchArgs B)
         // the first wave took the agent-scope acquire after its waits, before
         // the barrier above (it invalidates the caches this workgroup reads
         // through, which all its waves share).
-        if constexpr (COLS && FL > 0) {
+        if constexpr (LD > 0) {
+            sweep_db_rows<FL == 4, CPT, LD, 3>(A, smem, tile);
+        } else if constexpr (COLS && FL > 0) {
             sweep_db_columns<FL == 4, CPT, FL>(A, smem, tile);
         } else if constexpr (COLS) {
             if (S.accept)
@@ -465,14 +473,16 @@ int grow_tables(okpz_batch *b, size_t nslots, size_t nphases, size_t ntiles)
     return OKPZ_OK;
 }
 
-template <int SCHEME, int CPT, bool COLS, int FL = 0>
+template <int SCHEME, int CPT, bool COLS, int FL = 0, int LD = 0>
 const void *batch_fn()
 {
-    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT, COLS, FL>);
+    return reinterpret_cast<const void *>(&batch_kernel<SCHEME, CPT, COLS, FL, LD>);
 }
 
-const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols, int fl)
+const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols, int fl, int ld)
 {
+    if (cpt == 2 && ld == 8) return fl == 4 ? batch_fn<kDB, 2, true, 4, 8>() : batch_fn<kDB, 2, true, 3, 8>();
+    if (cpt == 2 && ld == 7) return fl == 4 ? batch_fn<kDB, 2, true, 4, 7>() : batch_fn<kDB, 2, true, 3, 7>();
 #define OKPZ_BATCH_CASES(S)                          \
     switch (cpt) {                                   \
     case 1: return batch_fn<S, 1, false>();          \
@@ -753,7 +763,26 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
                 slots[i].a.rounds % (128u >> fl) != 0u)
                 fl = 0;
     }
-    const void *fn = batch_kernel_for(b->scheme, cpt, cols, fl);
+    // square 128- or 256-site domains of 8 x 8-site cells throughout: the
+    // row-paired sweep (its own LDS size)
+    // row-paired sweep (its own LDS size), two cells per lane: four per lane
+    // take twice the lanes
+    int ld = 0;
+    if (fl > 0 && (cpt == 2 || (cpt == 4 && 2 * nt <= (uint32_t)kMaxStepThreads))) {
+        const uint32_t d0 = slots[0].a.Dx;
+        ld = d0 == 256u ? 8 : d0 == 128u ? 7 : 0;
+        for (uint32_t i = 0; i < n && ld; ++i) {
+            const StepArgs &a = slots[i].a;
+            if (a.Dx != d0 || a.Dy != d0 || a.log2Cx != 3u || a.log2Cy != 3u || a.s_bits != 6u) ld = 0;
+        }
+        if (ld && cpt == 4) {
+            nt *= 2;
+            cpt = 2;
+        }
+        if (ld == 8) lds = 4u * rowpair_lds_words<8, 3>(nt);
+        if (ld == 7) lds = 4u * rowpair_lds_words<7, 3>(nt);
+    }
+    const void *fn = batch_kernel_for(b->scheme, cpt, cols, fl, ld);
     if (!fn) return OKPZ_EINVAL;
     if (lds > 64u * 1024u)
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLds - kStaticLds)));
@@ -782,7 +811,8 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         k += sizeof(uint32_t) * (n + 1);
         std::memcpy(k, phases.data(), sizeof(BatchPhase) * phases.size());
         k += sizeof(BatchPhase) * phases.size();
-        const uint32_t shape[4] = {nt, cpt | (cols ? 0x100u : 0u) | ((uint32_t)fl << 16), grid, b->use_graph ? 1u : 0u};
+        const uint32_t shape[4] = {nt, cpt | (cols ? 0x100u : 0u) | ((uint32_t)fl << 16) | ((uint32_t)ld << 24), grid,
+                                   b->use_graph ? 1u : 0u};
         std::memcpy(k, shape, sizeof(shape));
     }
     std::vector<int32_t> table_slot(order.begin(), order.end());

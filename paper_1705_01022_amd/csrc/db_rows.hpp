@@ -82,14 +82,21 @@ __device__ __forceinline__ void copy_window_rows(const StepArgs &A, uint32_t *ld
 // rates as described above).  pre: the attempt's acceptance prefix (ACCEPT).
 // enable: false for attempts that run in a later pass.  rho, cell, tile:
 // the counters of the tie-break draw.
-// A word of the workgroup's LDS by byte address.  The row-paired kernels
-// declare no static LDS, so their dynamic LDS (the window first) starts at
-// LDS address 0 and a byte offset into it is the LDS address itself.
+// A word of the workgroup's LDS by its LDS byte address.
 using lds_word = __attribute__((address_space(3))) uint32_t;
 
 __device__ __forceinline__ lds_word *lds_at(uint32_t byte_addr)
 {
     return reinterpret_cast<lds_word *>(static_cast<uintptr_t>(byte_addr));
+}
+
+// LDS byte address of a pointer into the workgroup's LDS (0 for the dynamic
+// LDS of a kernel without static LDS).
+__device__ __forceinline__ uint32_t lds_address(const uint32_t *p)
+{
+    // a C-style cast is the address-space conversion
+    const __attribute__((address_space(3))) uint32_t *q = (const __attribute__((address_space(3))) uint32_t *)p;
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(q));
 }
 
 // (a << sh) | b in one instruction (the compiler otherwise folds two such
@@ -159,7 +166,8 @@ __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint
 // Linear site of a DB lane draw: site (du, dv) = (field mod C, field / C mod
 // C) of the cell whose corner, with the round's cell-grid shift, is
 // (cu, cv) -- both wrap around the domain (Sec. 3.1 DB: the shifted cell grid
-// is periodic on the domain); origin = the window index of domain site (0,0).
+// is periodic on the domain); origin = the linear index of domain site
+// (0, 0), counted from LDS address 0.
 // wrapv = false: the caller knows the row cannot pass the domain's last row
 // (only cells of the last cell row can wrap vertically).
 template <int LD, int LC>
@@ -203,7 +211,10 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
     const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
     const uint32_t X0 = (A.ox + 2u * S::D * tx + A.set_a * S::D) & A.L_mask;
     const uint32_t Y0 = (A.oy + 2u * S::D * ty + A.set_b * S::D) & A.L_mask;
-    const uint32_t origin = (Y0 & 3u) * S::ROW + (X0 & 31u);  // window index of domain site (0, 0)
+    // linear index of domain site (0, 0), counted from LDS address 0: the
+    // window's own LDS address (a multiple of 4 bytes, so whole words) is
+    // 8 bits per byte further on
+    const uint32_t origin = (Y0 & 3u) * S::ROW + (X0 & 31u) + 8u * lds_address(lds);
 
     copy_window_rows<true, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
 

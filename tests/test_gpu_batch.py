@@ -205,3 +205,26 @@ def test_batch_db_column_sweep_1024_cells(okpz, orc, threads):
     b.config(threads, 0, True)
     run_both(b, lats, mirrors, mix, [m[5] for m in mix])
     b.close()
+
+
+ROW_MIXES = {
+    # every member DB with square 256- or 128-site domains of 8 x 8-site cells
+    # and one lane-field width: the batch kernel's row-paired sweep
+    "D256_accept": [(512, 256, 8, 0.95, 0.05, 3), (1024, 256, 8, 0.7, 0.3, 2), (512, 256, 8, 0.5, 0.5, 4)],
+    "D256_p1": [(512, 256, 8, 1.0, 0.0, 3), (1024, 256, 8, 0.0, 1.0, 2)],
+    "D128_accept": [(256, 128, 8, 0.9, 0.1, 3), (512, 128, 8, 0.6, 0.4, 2), (256, 128, 8, 0.999, 0.001, 5)],
+}
+
+
+@pytest.mark.parametrize("threads", [0, 256, 512])
+@pytest.mark.parametrize("mix", sorted(ROW_MIXES))
+def test_batch_db_row_sweep(okpz, orc, mix, threads):
+    """Batches whose members all take the row-paired DB sweep (two cells per
+    lane, whatever width is configured): the oracle's results, including a
+    second run that replays the captured launch."""
+    m = ROW_MIXES[mix]
+    b, lats, mirrors = make_batch(okpz, orc, 1, m)
+    b.config(threads, 0, True)
+    run_both(b, lats, mirrors, m, [x[5] for x in m])
+    run_both(b, lats, mirrors, m, [x[5] for x in m])
+    b.close()
