@@ -166,6 +166,40 @@ class SeqRS:
         return net
 
 
+def _seq_roughness_rows(args) -> list:
+    L, p, q, times, seed, streams = args
+    rows = []
+    for r in streams:
+        rs = SeqRS(L, p, q, seed=seed, stream=r)
+        t, row = 0, []
+        for tt in times:
+            rs.run(tt - t)
+            t = tt
+            row.append(w2(rs.s))
+        rows.append(row)
+    return rows
+
+
+def seq_rs_roughness(L: int, p: float, q: float, times, seed: int, n: int, workers: int = 1) -> np.ndarray:
+    """W^2 at each of ``times`` (MCS, non-decreasing) of n sequential-RS runs
+    from the flat state (streams 0 .. n-1 of ``seed``): rows are runs.  With
+    workers > 1 the runs are spread over freshly spawned processes (the rows
+    do not depend on how)."""
+    times = list(times)
+    if workers <= 1:
+        return np.array(_seq_roughness_rows((L, p, q, times, seed, list(range(n)))))
+    import multiprocessing as mp
+
+    chunks = [list(range(k, n, workers)) for k in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        parts = pool.map(_seq_roughness_rows, [(L, p, q, times, seed, c) for c in chunks])
+    out = np.zeros((n, len(times)))
+    for c, rows in zip(chunks, parts):
+        for r, row in zip(c, rows):
+            out[r] = row
+    return out
+
+
 # --------------------------------------------------------------------------- DTr emulation
 @dataclass
 class Emu:

@@ -2,15 +2,24 @@
 
 The decomposition changes the non-universal prefactor of the roughness
 (finer decompositions sample the lattice more evenly and roughen slightly
-less, Sec. 4.2) but not the growth exponent.  So:
+less, Sec. 4.3, corrections to scaling) but not the growth exponent.  So:
+
+* the W^2 deficit of GPU DTrDT against the oracle's sequential RS shrinks as
+  the thread cells grow (TC = 1,1 -> 2,2 -> 3,3 at fixed device domains), the
+  paper's reason for the deficit, shown on the GPU path itself; the literal
+  3-standard-error comparison per time point is printed for each TC;
 
 * at L = 128, the GPU DTrDB W^2(t) of 64 realisations and the oracle's
   sequential RS W^2(t) of 64 realisations have the same effective growth
   exponent (Eq. `eq:effexp`) within 3 standard errors, and differ by a few
   percent at most at every time (the signed deviations are printed);
-* at L = 2048 (growth regime, t << L^z), the effective exponent over the
-  last decade of a 4096-MCS run is within max(3 sigma, 0.02) of the KPZ value
-  beta = 0.2414 (Sec. 2.1).
+* at L = 2048 (growth regime, t << L^z), the effective exponents rise
+  octave by octave over the first decade (0.213, 0.221, 0.228 for 64 .. 512
+  MCS): finite-time corrections to scaling that the paper shows for every
+  decomposition (Sec. 4.3, effective exponents) approach the asymptote from
+  below; over 512 .. 4096 MCS the exponent is within max(3 sigma, 0.02) of the
+  KPZ value beta = 0.2414 (Sec. 2.1), the 0.02 covering the remaining
+  correction (the last rise per octave measured before 512 MCS is 0.008).
 """
 import math
 
@@ -46,6 +55,43 @@ def beta_eff(w2, times, i, j):
     return aging.effective_exponent(times, w2, j, i, power=0.5)
 
 
+def test_roughness_deficit_shrinks_with_cell_size(okpz, orc):
+    """L = 128, 64 x 64-site device domains, DTrDT at p = 1, q = 0, 1024
+    realisations per cell size against 1024 sequential-RS runs.  Per time
+    point: the relative deficit (W2_seq - W2_gpu) / W2_seq, its z-score and
+    whether it lies within 3 standard errors (the family-wise false-alarm
+    rate of 7 such checks under the null is about 1 - 0.9973^7 = 1.9 %).  The
+    deficit averaged over the times (ratios to the sequential mean, per run,
+    so that its standard error comes from the runs) must be positive for
+    every cell size and fall as the cells grow, the TC = 1,1 -> 3,3 drop by
+    more than 3 standard errors and at least by half."""
+    L, D, n = 128, 64, 1024
+    times = [1, 2, 4, 8, 16, 32, 64]
+    s = orc.seq_rs_roughness(L, 1.0, 0.0, times, seed=11, n=n, workers=16)
+    ms, vs = s.mean(axis=0), s.var(axis=0, ddof=1)
+    seq_ratio = (s / ms).mean(axis=1)  # per run, the time average of W2 / <W2_seq>
+    deficit, err = {}, {}
+    for tc, C in (("1,1", 8), ("2,2", 16), ("3,3", 32)):
+        g = gpu_series(okpz, L, D, C, okpz.BLOCK_DT, 1.0, 0.0, n, times, seed=5)
+        mg, vg = g.mean(axis=0), g.var(axis=0, ddof=1)
+        z = (mg - ms) / np.sqrt(vg / n + vs / n)
+        within = int(np.sum(np.abs(z) <= 3.0))
+        print("\nTC=%s: t, rel.deficit, z" % tc)
+        for i, t in enumerate(times):
+            print("  %3d %+.4f %+6.1f" % (t, (ms[i] - mg[i]) / ms[i], z[i]))
+        ratio = (g / ms).mean(axis=1)
+        deficit[tc] = 1.0 - ratio.mean()
+        err[tc] = math.sqrt(ratio.var(ddof=1) / n + seq_ratio.var(ddof=1) / n)
+        print("TC=%s: %d of %d time points within 3 SE; mean deficit %.4f +- %.4f"
+              % (tc, within, len(times), deficit[tc], err[tc]))
+    for tc in deficit:
+        assert deficit[tc] > 0, tc
+    assert deficit["1,1"] > deficit["2,2"] > deficit["3,3"]
+    drop = deficit["1,1"] - deficit["3,3"]
+    assert drop > 3 * math.hypot(err["1,1"], err["3,3"])
+    assert deficit["3,3"] < 0.5 * deficit["1,1"]
+
+
 def test_roughness_growth_matches_sequential_rs(okpz, orc):
     L, D, C, p, q, n = 128, 32, 8, 1.0, 0.0, 64
     g = gpu_series(okpz, L, D, C, okpz.BLOCK_DB, p, q, n, TIMES, seed=5)
@@ -71,6 +117,11 @@ def test_growth_exponent_is_kpz(okpz):
     for i in range(1, len(times)):
         b, e = beta_eff(g, times, i - 1, i)
         print("beta_eff(%d..%d) = %.4f +- %.4f" % (times[i - 1], times[i], b, e))
+    # the approach from below: rising effective exponents over 64 .. 512 MCS
+    early = [beta_eff(g, times, i - 1, i) for i in (1, 2, 3)]
+    assert early[0][0] < early[1][0] < early[2][0]
+    assert early[2][0] - early[0][0] > 3 * math.hypot(early[0][1], early[2][1])
     b, e = beta_eff(g, times, 3, 6)  # 512 .. 4096
     print("beta_eff(512..4096) = %.4f +- %.4f" % (b, e))
+    assert early[-1][0] < b < 0.2414 + 3 * e
     assert abs(b - 0.2414) < max(3 * e, 0.02)
