@@ -285,8 +285,16 @@ def _serve_window(okpz, reqs, time_scale=1.0, chunk_mcs=64):
         if wait > 0:
             time.sleep(wait)
         srv.submit(r.L, r.Dx, r.Dy, r.Cx, r.Cy, r.scheme, 1, r.rid, r.n_mcs, r.p, r.q)
-    srv.drain(1200.0)
-    res = srv.poll(len(reqs) + 8)
+    # collect results as they finish (a line every 25 finished requests)
+    res, reported, t_end = [], 0, time.perf_counter() + 1200.0
+    while len(res) < len(reqs) and time.perf_counter() < t_end:
+        time.sleep(0.2)
+        res += srv.poll(len(reqs) + 8)
+        if len(res) >= reported + 25:
+            reported = len(res) - len(res) % 25
+            print("bench: served %d of %d requests" % (len(res), len(reqs)), file=sys.stderr, flush=True)
+    srv.drain(60.0)
+    res += srv.poll(len(reqs) + 8)
     st = srv.stats()
     srv.close()
     assert len(res) == len(reqs) and all(x["status"] == 0 for x in res)
