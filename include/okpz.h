@@ -13,7 +13,8 @@
  * Conventions
  *   - Sites (x, y) in [0, L)^2, periodic, x fast.  Slope bits per site:
  *     sx = 1 iff h(x,y) - h(x-1,y) = +1, sy = 1 iff h(x,y) - h(x,y-1) = +1
- *     (one slope per direction is stored on the site, Sec. 3, DB scheme).
+ *     (each site keeps its slopes towards the left and lower neighbours,
+ *     Sec. 3, DB scheme).
  *   - Host site arrays ("sites") are L*L bytes, index y*L + x,
  *     bit 0 = sx, bit 1 = sy, other bits zero.
  *   - Packed device layout ("words", 2 bits per site as in the paper's
