@@ -328,8 +328,8 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const uint32_t *band_
                                                            const int64_t *__restrict__ partial,
                                                            int64_t *__restrict__ out)
 {
-    __shared__ uint64_t lo_s[kMomentFields][256];
-    __shared__ int64_t hi_s[kMomentFields][256];
+    __shared__ uint64_t lo_s[kMomentFields][kReduceMaxWaves];
+    __shared__ int64_t hi_s[kMomentFields][kReduceMaxWaves];
     const uint32_t r = blockIdx.x;
     reduce_body(partial + static_cast<uint64_t>(band_prefix[r]) * kMomentFields, band_prefix[r + 1] - band_prefix[r],
                 out + 2 * kMomentFields * r, lo_s, hi_s);

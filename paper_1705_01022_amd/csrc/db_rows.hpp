@@ -32,17 +32,23 @@ namespace okpz {
 
 // Compile-time geometry of a square D x D domain (LD = log2 D >= 5) with
 // C x C-site cells (LC = log2 C): the same window as window_shape() on the
-// host (NWX blocks, NB bands, odd sx pitch P).
+// host (NWX blocks, NB bands).
 template <int LD, int LC>
 struct RowPairShape {
     static constexpr uint32_t D = 1u << LD;
     static constexpr uint32_t C = 1u << LC;
     static constexpr uint32_t NWX = D / 32 + 1;
-    static constexpr uint32_t P = (NWX + 1) | 1u;
+    // the sy words of a row start right after its sx words: an attempt also
+    // reads the word after its sx word, which for the last block is the
+    // first sy word -- read but never used or written, since a domain site
+    // (window column <= D - 1 + 31) is never bit 31 of the last block
+    static constexpr uint32_t P = NWX | 1u;
     static constexpr uint32_t NB = D / 4 + 1;
     static constexpr uint32_t NR = 4 * NB;
     // words per window row (sx words, sy words, one pad word): odd, so that
-    // rows 32 apart -- the two lane rows of a wave -- fall on different banks
+    // rows 32 apart -- the two lane rows of a wave -- fall on different
+    // banks; 19 words at D = 256 keep the window and the published sites of
+    // 256 lanes within a seventh of the compute unit's LDS
     static constexpr uint32_t PITCH = 2 * P + 1;
     static constexpr uint32_t ROW = 32 * PITCH;      // bits per window row (linear site index stride)
     static constexpr uint32_t NCX = D / C;           // cells per domain row
@@ -354,10 +360,10 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
     copy_window_rows<false, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
 }
 
-// The device-step kernel on the row-paired window, held to six waves per
-// SIMD (its LDS allows six 256-lane workgroups per compute unit).
+// The device-step kernel on the row-paired window, held to seven waves per
+// SIMD (its LDS allows seven 256-lane workgroups per compute unit).
 template <bool ACCEPT, int CPT, int LD, int LC>
-__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(kMaxStepThreads) __attribute__((amdgpu_waves_per_eu(7)))
 step_db_rows_kernel(StepArgs A)
 {
     extern __shared__ uint32_t smem[];

@@ -894,23 +894,40 @@ __global__ void __launch_bounds__(kMaxStepThreads) step_kernel(StepArgs A)
 // Heights (gauge h(0,0) = 0): h(0,y) = sum_{y'=1..y} (2 sy[0,y'] - 1);
 // h(x,y) = h(0,y) + sum_{x'=1..x} (2 sx[x',y] - 1).
 
-// Column-0 anchors h(0,y): one workgroup; each thread owns a run of bands,
-// reads the sy words of block 0 of each band, and a block scan joins the runs.
+// Column-0 anchors h(0,y): one workgroup; each thread owns a run of up to
+// 32 consecutive bands (L <= 2^17 with 1024 threads), reads the sy words of
+// block 0 of each band -- eight loads in flight at a time -- and keeps the
+// run's column-0 bits in registers (bit 4k + r: row r of the run's band k);
+// a block scan joins the runs and each thread writes its rows' heights, four
+// at a time.
 __device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words, uint32_t L, uint32_t nbx_log2,
                                              int32_t *__restrict__ h0, int32_t *part)
 {
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     const uint32_t nband = L >> 2;
-    const uint32_t chunk = (nband + T - 1) / T;
+    const uint32_t chunk = (nband + T - 1) / T;  // at most 32
     const uint32_t b0 = tid * chunk;
-    int32_t local = 0;
-    for (uint32_t k = 0; k < chunk; ++k) {
-        const uint32_t b = b0 + k;
-        if (b >= nband) break;
-        const uint4 sy = *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b) << nbx_log2) << 3) + 4);
-        const int32_t bits = (int32_t)((sy.x & 1u) + (sy.y & 1u) + (sy.z & 1u) + (sy.w & 1u));
-        local += b == 0 ? 2 * (bits - (int32_t)(sy.x & 1u)) - 3 : 2 * bits - 4;  // row 0 has no step
+    const uint32_t nb = b0 < nband ? min(chunk, nband - b0) : 0u;
+    uint32_t bits[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (uint32_t g = 0; g < 4; ++g) {
+        if (8u * g >= nb) break;
+        uint32_t v = 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+            const uint32_t k = 8u * g + i;
+            if (k < nb) {
+                const uint4 sy =
+                    *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b0 + k) << nbx_log2) << 3) + 4);
+                v |= ((sy.x & 1u) | (sy.y & 1u) << 1 | (sy.z & 1u) << 2 | (sy.w & 1u) << 3) << (4u * i);
+            }
+        }
+        bits[g] = v;
     }
+    // height change over the run: +1 per bit, -1 per row, row 0 of the lattice has no step
+    int32_t local = 2 * (int32_t)(__popc(bits[0]) + __popc(bits[1]) + __popc(bits[2]) + __popc(bits[3])) -
+                    4 * (int32_t)nb;
+    if (b0 == 0u && nb > 0u) local -= 2 * (int32_t)(bits[0] & 1u) - 1;
     part[tid] = local;
     __syncthreads();
     for (uint32_t off = 1; off < T; off <<= 1) {  // inclusive Hillis-Steele scan
@@ -920,16 +937,22 @@ __device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words,
         __syncthreads();
     }
     int32_t h = part[tid] - local;  // exclusive prefix: h(0, 4 b0 - 1)
-    for (uint32_t k = 0; k < chunk; ++k) {
-        const uint32_t b = b0 + k;
-        if (b >= nband) break;
-        const uint4 sy = *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b) << nbx_log2) << 3) + 4);
-        const uint32_t r4[4] = {sy.x, sy.y, sy.z, sy.w};
 #pragma unroll
-        for (uint32_t r = 0; r < 4; ++r) {
-            const uint32_t y = 4 * b + r;
-            if (y > 0) h += 2 * (int32_t)(r4[r] & 1u) - 1;
-            h0[y] = h;
+    for (uint32_t g = 0; g < 4; ++g) {
+        if (8u * g >= nb) break;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+            const uint32_t k = 8u * g + i;
+            if (k < nb) {
+                const uint32_t nib = bits[g] >> (4u * i);
+                int4 hv;
+                hv.x = (b0 + k == 0u) ? h : h + 2 * (int32_t)(nib & 1u) - 1;
+                hv.y = hv.x + 2 * (int32_t)((nib >> 1) & 1u) - 1;
+                hv.z = hv.y + 2 * (int32_t)((nib >> 2) & 1u) - 1;
+                hv.w = hv.z + 2 * (int32_t)((nib >> 3) & 1u) - 1;
+                h = hv.w;
+                *reinterpret_cast<int4 *>(h0 + 4u * (b0 + k)) = hv;
+            }
         }
     }
 }
@@ -1185,45 +1208,60 @@ __device__ __forceinline__ void add_i128(uint64_t &lo, int64_t &hi, uint64_t blo
     lo = nlo;
 }
 
-// Final exact reduction of the per-row partials into 128-bit totals.
-// One workgroup of 256 lanes: 128-bit totals of nrows rows of partials.
+// Final exact reduction of the per-row partials into 128-bit totals, one
+// workgroup of up to 1024 lanes: each lane accumulates rows tid, tid + T, ...
+// (the six fields of a row are one 48-byte record; four rows in flight), a
+// wave sums its lanes by shuffles, and the first lanes add the waves'.
+constexpr int kReduceMaxWaves = 16;
+
 __device__ __forceinline__ void reduce_body(const int64_t *__restrict__ partial, uint32_t nrows,
-                                            int64_t *__restrict__ out, uint64_t (*lo_s)[256], int64_t (*hi_s)[256])
+                                            int64_t *__restrict__ out, uint64_t (*lo_s)[kReduceMaxWaves],
+                                            int64_t (*hi_s)[kReduceMaxWaves])
 {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    uint64_t lo[kMomentFields];
+    int64_t hi[kMomentFields];
+#pragma unroll
     for (int f = 0; f < kMomentFields; ++f) {
-        uint64_t lo = 0;
-        int64_t hi = 0;
-        for (uint32_t r = tid; r < nrows; r += blockDim.x) {
-            const int64_t v = partial[static_cast<uint64_t>(r) * kMomentFields + f];
-            add_i128(lo, hi, static_cast<uint64_t>(v), v < 0 ? -1 : 0);
+        lo[f] = 0;
+        hi[f] = 0;
+    }
+#pragma unroll 4
+    for (uint32_t r = tid; r < nrows; r += blockDim.x) {
+        const int64_t *row = partial + static_cast<uint64_t>(r) * kMomentFields;
+#pragma unroll
+        for (int f = 0; f < kMomentFields; ++f) add_i128(lo[f], hi[f], static_cast<uint64_t>(row[f]), row[f] < 0 ? -1 : 0);
+    }
+#pragma unroll
+    for (int f = 0; f < kMomentFields; ++f) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t olo = __shfl_xor(lo[f], off, 64);
+            const int64_t ohi = __shfl_xor(hi[f], off, 64);
+            add_i128(lo[f], hi[f], olo, ohi);
         }
-        lo_s[f][tid] = lo;
-        hi_s[f][tid] = hi;
+        if (lane == 0) {
+            lo_s[f][wave] = lo[f];
+            hi_s[f][wave] = hi[f];
+        }
     }
     __syncthreads();
-    for (uint32_t off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (tid < off)
-            for (int f = 0; f < kMomentFields; ++f) {
-                uint64_t lo = lo_s[f][tid];
-                int64_t hi = hi_s[f][tid];
-                add_i128(lo, hi, lo_s[f][tid + off], hi_s[f][tid + off]);
-                lo_s[f][tid] = lo;
-                hi_s[f][tid] = hi;
-            }
-        __syncthreads();
-    }
     if (tid < kMomentFields) {
-        out[2 * tid] = static_cast<int64_t>(lo_s[tid][0]);
-        out[2 * tid + 1] = hi_s[tid][0];
+        uint64_t tlo = 0;
+        int64_t thi = 0;
+        for (uint32_t w = 0; w < nwaves; ++w) add_i128(tlo, thi, lo_s[tid][w], hi_s[tid][w]);
+        out[2 * tid] = static_cast<int64_t>(tlo);
+        out[2 * tid + 1] = thi;
     }
 }
 
-static __global__ void __launch_bounds__(256) reduce_kernel(const int64_t *__restrict__ partial, uint32_t nrows,
-                                                     int64_t *__restrict__ out)
+constexpr int kReduceThreads = 1024;
+
+static __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const int64_t *__restrict__ partial,
+                                                                       uint32_t nrows, int64_t *__restrict__ out)
 {
-    __shared__ uint64_t lo_s[kMomentFields][256];
-    __shared__ int64_t hi_s[kMomentFields][256];
+    __shared__ uint64_t lo_s[kMomentFields][kReduceMaxWaves];
+    __shared__ int64_t hi_s[kMomentFields][kReduceMaxWaves];
     reduce_body(partial, nrows, out, lo_s, hi_s);
 }
 

@@ -78,7 +78,7 @@ extern "C" int okpz_measure_noalloc(const void *dev_words, uint32_t L, void *hip
     hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, st, words, L, nbx_log2, h0);
     hipLaunchKernelGGL((rows_kernel<false>), dim3(blocks), dim3(kMeasureThreads), 0, st, words, h0, nullptr,
                        nullptr, L, nbx_log2, partial);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partial, L / 4, dev_totals);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduceThreads), 0, st, partial, L / 4, dev_totals);
     HIP_TRY(hipGetLastError());
     if (out) {
         int64_t totals[2 * kMomentFields];

@@ -168,7 +168,7 @@ int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_
     else
         hipLaunchKernelGGL((rows_kernel<false>), dim3(blocks), dim3(kMeasureThreads), 0, lat->stream, src, h0_dst,
                            nullptr, nullptr, p.L, nbx_log2, lat->partial);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, lat->stream, lat->partial, p.L / 4, lat->reduced);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduceThreads), 0, lat->stream, lat->partial, p.L / 4, lat->reduced);
     end_timed(lat, tp);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(lat->host_out, lat->reduced, 2 * kMomentFields * sizeof(int64_t),
