@@ -16,9 +16,12 @@
 //    s mod 32 (the shift instructions read only the low five bits), and the
 //    sites to the right and below are s + 1 and s + 32W, which is all the
 //    delayed-border dependency checks compare.
-//  * Acceptance is decided after the slopes are read: only a local minimum
-//    (deposition, threshold P) or a local maximum (removal, threshold Q) is
-//    compared with its acceptance prefix, and the 32-bit tie-break draw is
+//  * Acceptance is decided after the slopes are read: whether the site is a
+//    local minimum or maximum is tested on the four slope words at once (two
+//    three-input bit operations; the site's bit of the result is then
+//    extracted), and only a local minimum (deposition, threshold P) or a
+//    local maximum (removal, threshold Q) is compared with its acceptance
+//    prefix, and the 32-bit tie-break draw is
 //    made only when that prefix equals the threshold's top bits -- for an
 //    attempt that can flip.  The variate and its thresholds are those of the
 //    generic kernels (U = prefix * 2^32 + r against P or Q), so the outcome
@@ -122,6 +125,15 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// f(a, b, c) bit by bit, f given by its truth table TT (bit 4a + 2b + c)
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bitop3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "v"(b), "v"(c), "i"(TT));
+    return r;
+}
+
 // 1 << (s mod 32) and 3 << (s mod 32), the flip masks of sx(x) and of
 // sx(x), sx(x+1) (shift instructions read the low five bits of s); written
 // as instructions so that the test for x = bit 31 stays one compare.
@@ -138,24 +150,32 @@ __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint
     lds_word *px = lds_at((s >> 3) & ~3u);
     const uint32_t w0 = px[0], w1 = px[1];
     const uint32_t y0 = px[P], y1 = px[P + PITCH];
-    // pattern index: bit 3 sx(x+1,y), bit 2 sx(x,y), bit 1 sy(x,y), bit 0
-    // sy(x,y+1); bit 4 holds a further sx bit (the masks repeat at +16)
-    const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, s);
     const uint32_t d = __builtin_amdgcn_ubfe(y1, s, 1);
-    const uint32_t key = lshl_or(ab, 2, lshl_or(__builtin_amdgcn_ubfe(y0, s, 1), 1, d));
     bool flip;
     if (ACCEPT) {
+        // bit s of mm: the slopes (sx(x), sx(x+1), sy(x,y), sy(x,y+1)) are
+        // (a, 1-a, a, 1-a), a local minimum (a = 0) or maximum (a = 1); e has
+        // sx(x+1) at the bit of x.  Two three-input operations:
+        // (e ^ w0) & ~(w0 ^ y0), then that & (y0 ^ y1).
+        const uint32_t e = __builtin_amdgcn_alignbit(w1, w0, 1u);
+        const uint32_t mm = bitop3<0x60>(bitop3<0x18>(e, w0, y0), y0, y1);
         // a minimum has sy(x,y+1) = 1, a maximum 0: the prefix is compared
         // with P_hi when d = 1, with Q_hi when d = 0, i.e. pre - d (P_hi - Q_hi)
-        // with Q_hi (signed: the shifted prefix can be negative)
-        const bool mm = enable && __builtin_amdgcn_ubfe(kFlipMin | kFlipMax, key, 1) != 0u;
+        // with Q_hi (signed: the shifted prefix can be negative); an attempt
+        // at neither compares INT_MAX instead
+        const int sel = __builtin_amdgcn_sbfe((int)mm, s, 1);  // -1 or 0
         const int rel = mad_i24((int)d, -A.pq_delta, (int)pre);
-        flip = mm && rel < (int)A.Q_hi;
-        if (mm && rel == (int)A.Q_hi) {  // the prefix ties: the low 32 bits of the variate decide
+        const int t = (rel & sel) | (0x7fffffff & ~sel);
+        flip = enable && t < (int)A.Q_hi;
+        if (enable && t == (int)A.Q_hi) {  // the prefix ties: the low 32 bits of the variate decide
             const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
             flip = r < (d ? A.P_lo : A.Q_lo);
         }
     } else {
+        // pattern index: bit 3 sx(x+1,y), bit 2 sx(x,y), bit 1 sy(x,y), bit 0
+        // sy(x,y+1); bit 4 holds a further sx bit (the masks repeat at +16)
+        const uint32_t ab = __builtin_amdgcn_alignbit(w1, w0, s);
+        const uint32_t key = lshl_or(ab, 2, lshl_or(__builtin_amdgcn_ubfe(y0, s, 1), 1, d));
         flip = enable && __builtin_amdgcn_ubfe(A.flip_table, key, 1) != 0u;
     }
     if (flip) {
