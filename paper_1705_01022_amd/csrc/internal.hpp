@@ -13,6 +13,7 @@
 
 #include "../../include/okpz.h"
 #include "db_rows.hpp"
+#include "dt_rows.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
 

@@ -79,12 +79,41 @@ bool launch_db_rows(uint32_t nt, uint32_t ntiles, hipStream_t st, const StepArgs
     return false;
 }
 
+// The row-paired DT / DTr kernel for square 128- or 256-site domains of
+// 8 x 8-site cells (4 site bits per lane draw, in 16-bit fields with
+// acceptance prefixes, 4-bit fields without), one to four cells per lane.
+template <int SCHEME, bool ACCEPT, int CPT>
+bool launch_dt_rows(uint32_t nt, uint32_t ntiles, hipStream_t st, const StepArgs &a, int &rc)
+{
+    if constexpr ((SCHEME == kDT || SCHEME == kDTR) && (CPT == 1 || CPT == 2 || CPT == 4)) {
+        constexpr uint32_t FL = ACCEPT ? 4u : 2u;
+        if (a.Dx != a.Dy || a.log2Cx != 3u || a.log2Cy != 3u || a.s_bits != 4u || a.F_log2 != FL ||
+            a.shared_edges)
+            return false;
+        if (a.Dx == 256u) {
+            rc = launch_instance(&step_dt_rows_kernel<SCHEME, ACCEPT, CPT, 8, 3>, nt, ntiles,
+                                 4u * rowpair_dt_lds_words<8, 3>(), st, a);
+            return true;
+        }
+        if (a.Dx == 128u) {
+            rc = launch_instance(&step_dt_rows_kernel<SCHEME, ACCEPT, CPT, 7, 3>, nt, ntiles,
+                                 4u * rowpair_dt_lds_words<7, 3>(), st, a);
+            return true;
+        }
+    }
+    return false;
+}
+
 // DB runs the row-paired kernel where it applies, else, with at least two
 // cells per lane and at most 64 cells per domain row, the column-mapped
 // kernel (same results, less bookkeeping than the generic one).
 template <int SCHEME, bool ACCEPT, int CPT>
 int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
+    if constexpr (SCHEME != kDB) {
+        int rc = OKPZ_OK;
+        if (launch_dt_rows<SCHEME, ACCEPT, CPT>(nt, ntiles, st, a, rc)) return rc;
+    }
     if constexpr (SCHEME == kDB && CPT >= 2) {
         int rc = OKPZ_OK;
         if (launch_db_rows<ACCEPT, CPT>(nt, ntiles, st, a, rc)) return rc;
