@@ -106,6 +106,9 @@ __device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint
 //
 // LD > 0 (with COLS and FL > 0): every lattice also has square 2^LD-site
 // domains of 8 x 8-site cells, so the row-paired DB sweep serves them all.
+// LD > 0 with DT or DTr: every lattice has square 128- or 256-site domains of
+// 8 x 8-site cells, and each item runs the row-paired DT sweep for its
+// lattice's domain size and rates.
 //
 // DT and DTr with at most 4 cells per lane: six waves per SIMD (80 VGPRs and
 // 40 bytes spilled to scratch; the LDS allows seven workgroups per compute
@@ -235,7 +238,19 @@ batch_kernel(BatchArgs B)
         // the first wave took the agent-scope acquire after its waits, before
         // the barrier above (it invalidates the caches this workgroup reads
         // through, which all its waves share).
-        if constexpr (LD > 0) {
+        if constexpr (LD > 0 && SCHEME != kDB) {
+            if (A.Dx == 256u) {
+                if (S.accept)
+                    sweep_dt_rows<SCHEME, true, CPT, 8, 3>(A, smem, tile);
+                else
+                    sweep_dt_rows<SCHEME, false, CPT, 8, 3>(A, smem, tile);
+            } else {
+                if (S.accept)
+                    sweep_dt_rows<SCHEME, true, CPT, 7, 3>(A, smem, tile);
+                else
+                    sweep_dt_rows<SCHEME, false, CPT, 7, 3>(A, smem, tile);
+            }
+        } else if constexpr (LD > 0) {
             sweep_db_rows<FL == 4, CPT, LD, 3>(A, smem, tile);
         } else if constexpr (COLS && FL > 0) {
             sweep_db_columns<FL == 4, CPT, FL>(A, smem, tile);
@@ -481,6 +496,17 @@ const void *batch_fn()
 
 const void *batch_kernel_for(int scheme, uint32_t cpt, bool cols, int fl, int ld)
 {
+    if (scheme != kDB && ld) {
+        switch (cpt * 4 + (uint32_t)(scheme == kDTR ? 1 : 0)) {
+        case 4: return batch_fn<kDT, 1, false, 0, 8>();
+        case 5: return batch_fn<kDTR, 1, false, 0, 8>();
+        case 8: return batch_fn<kDT, 2, false, 0, 8>();
+        case 9: return batch_fn<kDTR, 2, false, 0, 8>();
+        case 16: return batch_fn<kDT, 4, false, 0, 8>();
+        case 17: return batch_fn<kDTR, 4, false, 0, 8>();
+        default: return nullptr;
+        }
+    }
     if (cpt == 2 && ld == 8) return fl == 4 ? batch_fn<kDB, 2, true, 4, 8>() : batch_fn<kDB, 2, true, 3, 8>();
     if (cpt == 2 && ld == 7) return fl == 4 ? batch_fn<kDB, 2, true, 4, 7>() : batch_fn<kDB, 2, true, 3, 7>();
 #define OKPZ_BATCH_CASES(S)                          \
@@ -781,6 +807,22 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         }
         if (ld == 8) lds = 4u * rowpair_lds_words<8, 3>(nt);
         if (ld == 7) lds = 4u * rowpair_lds_words<7, 3>(nt);
+    }
+    // DT / DTr with square 128- or 256-site domains of 8 x 8-site cells
+    // throughout, at most four cells per lane: the row-paired DT sweep (the
+    // window alone in LDS)
+    if (b->scheme != kDB && cpt <= 4) {
+        bool rows = true, any256 = false;
+        for (uint32_t i = 0; i < n && rows; ++i) {
+            const StepArgs &a = slots[i].a;
+            rows = a.Dx == a.Dy && (a.Dx == 256u || a.Dx == 128u) && a.log2Cx == 3u && a.log2Cy == 3u &&
+                   a.s_bits == 4u && !a.shared_edges && a.F_log2 == (slots[i].accept ? 4u : 2u);
+            any256 = any256 || a.Dx == 256u;
+        }
+        if (rows) {
+            ld = 8;
+            lds = 4u * (any256 ? rowpair_dt_lds_words<8, 3>() : rowpair_dt_lds_words<7, 3>());
+        }
     }
     const void *fn = batch_kernel_for(b->scheme, cpt, cols, fl, ld);
     if (!fn) return OKPZ_EINVAL;

@@ -49,7 +49,11 @@ __device__ __forceinline__ void sweep_dt_rows(const StepArgs &A, uint32_t *smem,
 
     copy_window_rows<true, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
 
-    const uint32_t cx = tid & (S::NCX - 1u), grp = tid >> S::LOG2NCX;
+    // lanes past the domain's cells (a batch sizes its workgroups for its
+    // largest domains) only stage the window and keep the barriers; they
+    // shadow the first cell row's lanes, so their reads stay in the window
+    const bool act = tid < S::NCX * S::NCX / CPT;
+    const uint32_t cx = tid & (S::NCX - 1u), grp = act ? tid >> S::LOG2NCX : 0u;
     const uint32_t base_u = cx << LC;
     const uint32_t base_v0 = (grp * CPT) << LC;   // top cell's corner row
     const uint32_t cell0 = (grp * CPT) * S::NCX + cx;
@@ -91,7 +95,7 @@ __device__ __forceinline__ void sweep_dt_rows(const StepArgs &A, uint32_t *smem,
                     if (j == CPT - 1) v &= S::D - 1u;
                 }
                 const uint32_t s = __umul24(v, S::ROW) + u + origin;
-                attempt_rows<ACCEPT, P, S::PITCH>(A, s, f >> SBITS, true, rho, cell0 + j * S::NCX, tile);
+                attempt_rows<ACCEPT, P, S::PITCH>(A, s, f >> SBITS, act, rho, cell0 + j * S::NCX, tile);
             }
             __syncthreads();
         }

@@ -228,3 +228,29 @@ def test_batch_db_row_sweep(okpz, orc, mix, threads):
     run_both(b, lats, mirrors, m, [x[5] for x in m])
     run_both(b, lats, mirrors, m, [x[5] for x in m])
     b.close()
+
+
+DT_ROW_MIXES = {
+    # DT / DTr members with square 128- and 256-site domains of 8 x 8-site
+    # cells, with and without acceptance prefixes in one batch (lane fields of
+    # 16 and 4 bits): the batch kernel's row-paired DT sweep, each item for its
+    # own domain size and rates; 128-site members leave lanes idle
+    "mixed": [(512, 256, 8, 1.0, 0.0, 3), (256, 128, 8, 0.5, 0.5, 4), (1024, 256, 8, 0.95, 0.05, 2),
+              (256, 128, 8, 1.0, 0.0, 5), (512, 256, 8, 0.3, 0.9, 2)],
+    "D128": [(256, 128, 8, 0.95, 0.05, 3), (512, 128, 8, 1.0, 0.0, 2)],
+}
+
+
+@pytest.mark.parametrize("threads", [0, 256, 512])
+@pytest.mark.parametrize("scheme", [0, 2], ids=["DT", "DTr"])
+@pytest.mark.parametrize("mix", sorted(DT_ROW_MIXES))
+def test_batch_dt_row_sweep(okpz, orc, mix, scheme, threads):
+    """Batches whose members all take the row-paired DT / DTr sweep: the
+    oracle's results, including a second run that replays the captured
+    launch."""
+    m = DT_ROW_MIXES[mix]
+    b, lats, mirrors = make_batch(okpz, orc, scheme, m)
+    b.config(threads, 0, True)
+    run_both(b, lats, mirrors, m, [x[5] for x in m])
+    run_both(b, lats, mirrors, m, [x[5] for x in m])
+    b.close()
