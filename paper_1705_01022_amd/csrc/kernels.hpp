@@ -894,14 +894,21 @@ __global__ void __launch_bounds__(kMaxStepThreads) step_kernel(StepArgs A)
 // Heights (gauge h(0,0) = 0): h(0,y) = sum_{y'=1..y} (2 sy[0,y'] - 1);
 // h(x,y) = h(0,y) + sum_{x'=1..x} (2 sx[x',y] - 1).
 
-// Column-0 anchors h(0,y): one workgroup; each thread owns a run of up to
-// 32 consecutive bands (L <= 2^17 with 1024 threads), reads the sy words of
-// block 0 of each band -- eight loads in flight at a time -- and keeps the
-// run's column-0 bits in registers (bit 4k + r: row r of the run's band k);
-// a block scan joins the runs and each thread writes its rows' heights, four
-// at a time.
-__device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words, uint32_t L, uint32_t nbx_log2,
-                                             int32_t *__restrict__ h0, int32_t *part)
+// Column-0 bits of band b: bit r = sy of row 4b + r at x = 0 (the sy words
+// of the band's block 0).
+__device__ __forceinline__ uint32_t col0_bits(const uint32_t *__restrict__ words, uint32_t nbx_log2, uint32_t b)
+{
+    const uint4 sy = *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b) << nbx_log2) << 3) + 4);
+    return (sy.x & 1u) | (sy.y & 1u) << 1 | (sy.z & 1u) << 2 | (sy.w & 1u) << 3;
+}
+
+// Column-0 anchors h(0,y) in one workgroup: each thread owns a run of up to 32
+// consecutive bands (L <= 2^17 with 1024 threads) whose column-0 bits it
+// holds in registers (bit 4k + r: row r of the run's band k, from `fetch(b)`,
+// eight fetches in flight at a time); a block scan joins the runs and each
+// thread writes its rows' heights, four at a time.
+template <typename Fetch>
+__device__ __forceinline__ void anchors_scan(Fetch fetch, uint32_t L, int32_t *__restrict__ h0, int32_t *part)
 {
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     const uint32_t nband = L >> 2;
@@ -916,11 +923,7 @@ __device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words,
 #pragma unroll
         for (uint32_t i = 0; i < 8; ++i) {
             const uint32_t k = 8u * g + i;
-            if (k < nb) {
-                const uint4 sy =
-                    *reinterpret_cast<const uint4 *>(words + ((static_cast<uint64_t>(b0 + k) << nbx_log2) << 3) + 4);
-                v |= ((sy.x & 1u) | (sy.y & 1u) << 1 | (sy.z & 1u) << 2 | (sy.w & 1u) << 3) << (4u * i);
-            }
+            if (k < nb) v |= fetch(b0 + k) << (4u * i);
         }
         bits[g] = v;
     }
@@ -957,11 +960,30 @@ __device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words,
     }
 }
 
-static __global__ void __launch_bounds__(1024) anchors_kernel(const uint32_t *__restrict__ words, uint32_t L,
-                                                       uint32_t nbx_log2, int32_t *__restrict__ h0)
+// Anchors straight from the lattice words (the batch: one workgroup per member).
+__device__ __forceinline__ void anchors_body(const uint32_t *__restrict__ words, uint32_t L, uint32_t nbx_log2,
+                                             int32_t *__restrict__ h0, int32_t *part)
+{
+    anchors_scan([&](uint32_t b) { return col0_bits(words, nbx_log2, b); }, L, h0, part);
+}
+
+// A single lattice in two launches: the column-0 bits of every band, one
+// lane per band across the whole device (one 16-byte read per band, L/4 of
+// them 32 L bytes apart: spread over many compute units rather than queued in
+// one), one byte per band into col0; then the scan, in one workgroup, over
+// those L/4 contiguous bytes.
+static __global__ void __launch_bounds__(256) col0_kernel(const uint32_t *__restrict__ words, uint32_t L,
+                                                          uint32_t nbx_log2, uint8_t *__restrict__ col0)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < (L >> 2)) col0[b] = (uint8_t)col0_bits(words, nbx_log2, b);
+}
+
+static __global__ void __launch_bounds__(1024) anchors_kernel(const uint8_t *__restrict__ col0, uint32_t L,
+                                                              int32_t *__restrict__ h0)
 {
     __shared__ int32_t part[1024];
-    anchors_body(words, L, nbx_log2, h0, part);
+    anchors_scan([&](uint32_t b) { return (uint32_t)col0[b]; }, L, h0, part);
 }
 
 // Exclusive prefix sum over the 64 lanes of a wave and the wave's total, by

@@ -75,7 +75,10 @@ extern "C" int okpz_measure_noalloc(const void *dev_words, uint32_t L, void *hip
     const uint32_t nbx_log2 = ilog2(L / 32);
     const uint32_t rows_per_block = kMeasureThreads / 64;
     const uint32_t blocks = (L / 4 + rows_per_block - 1) / rows_per_block;
-    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, st, words, L, nbx_log2, h0);
+    // the partials region first holds the column-0 bytes (one per band)
+    uint8_t *col0 = reinterpret_cast<uint8_t *>(partial);
+    hipLaunchKernelGGL(col0_kernel, dim3((L / 4 + 255) / 256), dim3(256), 0, st, words, L, nbx_log2, col0);
+    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, st, col0, L, h0);
     hipLaunchKernelGGL((rows_kernel<false>), dim3(blocks), dim3(kMeasureThreads), 0, st, words, h0, nullptr,
                        nullptr, L, nbx_log2, partial);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduceThreads), 0, st, partial, L / 4, dev_totals);

@@ -188,7 +188,10 @@ int run_measure(okpz_lattice *lat, bool cross, const uint32_t *src, int32_t *h0_
     const uint32_t nbx_log2 = ilog2(p.L / 32);
     TimedPair tp;
     begin_timed(lat, 1, tp);
-    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, lat->stream, src, p.L, nbx_log2, h0_dst);
+    // the partials buffer (48 bytes per band) first holds the column-0 bytes (one per band)
+    uint8_t *col0 = reinterpret_cast<uint8_t *>(lat->partial);
+    hipLaunchKernelGGL(col0_kernel, dim3((p.L / 4 + 255) / 256), dim3(256), 0, lat->stream, src, p.L, nbx_log2, col0);
+    hipLaunchKernelGGL(anchors_kernel, dim3(1), dim3(1024), 0, lat->stream, col0, p.L, h0_dst);
     const uint32_t rows_per_block = kMeasureThreads / 64;
     const uint32_t blocks = (p.L / 4 + rows_per_block - 1) / rows_per_block;
     if (cross)
