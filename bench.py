@@ -43,14 +43,14 @@ VALU_PEAK_GOPS = CUS * SIMDS_PER_CU * 16 * CLOCK_GHZ
 DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/db_rows.hpp",
                   "paper_1705_01022_amd/csrc/okpz.hip", "paper_1705_01022_amd/csrc/philox.hpp",
                   "paper_1705_01022_amd/csrc/internal.hpp")
-MEASURED = {"sources": "0da5394a70ca8ba7", "workload": "L131072",
+MEASURED = {"sources": "672692955e38b43f", "workload": "L131072",
             # per launch of step_db_rows_kernel<true, 4, 8, 3>, averages of 12 dispatches
-            "FETCH_SIZE_KiB": 878214.8, "WRITE_SIZE_KiB": 1550412.6,
-            "SQ_INSTS_VALU": 2.7491746e9, "SQ_ACTIVE_INST_VALU": 2.7491746e9, "SQ_INSTS_SALU": 1.9342689e9,
-            "SQ_INSTS_LDS": 5.854008e8, "SQ_LDS_IDX_ACTIVE": 2.6336622e9, "SQ_LDS_BANK_CONFLICT": 1.0205468e9,
-            "SQ_WAIT_INST_LDS": 2.2681591e9,
+            "FETCH_SIZE_KiB": 904909.0, "WRITE_SIZE_KiB": 1454860.0,
+            "SQ_INSTS_VALU": 2.79393e9, "SQ_ACTIVE_INST_VALU": 2.79393e9, "SQ_INSTS_SALU": 1.84403e9,
+            "SQ_INSTS_LDS": 5.85401e8, "SQ_LDS_IDX_ACTIVE": 2.74260e9, "SQ_LDS_BANK_CONFLICT": 1.12949e9,
+            "SQ_WAIT_INST_LDS": 4.06227e9,
             # GRBM_GUI_ACTIVE summed over the 8 XCDs, divided by 8: the dispatch's GPU cycles
-            "GRBM_GUI_ACTIVE": 118811935.0 / 8, "launch_ms": 6.2771}
+            "GRBM_GUI_ACTIVE": 113589000.0 / 8, "launch_ms": 5.9732}
 
 
 def device_sources_hash() -> str:

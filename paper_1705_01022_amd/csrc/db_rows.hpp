@@ -168,7 +168,12 @@ __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint
         const int t = (rel & sel) | (0x7fffffff & ~sel);
         flip = enable && t < (int)A.Q_hi;
         if (enable && t == (int)A.Q_hi) {  // the prefix ties: the low 32 bits of the variate decide
-            const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, cell | 0x80000000u, tile, A.c3).x;
+            // the tie counter formed here, where the rare branch runs: as a
+            // loop-invariant value the compiler would keep its first Philox
+            // products in registers for the whole sweep
+            uint32_t c1;
+            asm volatile("v_or_b32 %0, 0x80000000, %1" : "=v"(c1) : "v"(cell));
+            const uint32_t r = philox4x32_10_lane(A.key0, A.key1, rho, c1, tile, A.c3).x;
             flip = r < (d ? A.P_lo : A.Q_lo);
         }
     } else {
