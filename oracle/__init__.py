@@ -32,6 +32,9 @@ _LIB = os.path.join(_HERE, "liboctaoracle.so")
 DT, DB, DTR = 0, 1, 2
 SCHEMES = {"DT": DT, "DB": DB, "DTR": DTR, "DTr": DTR}
 ORIGIN_RANDOM, ORIGIN_FIXED, ORIGIN_COARSE = 0, 1, 2
+# device layer: double tiling (four domain sets per MCS) or dead border (every
+# tile at once, its last column and row inactive; Sec. 3 DB, cDB with ORIGIN_COARSE)
+DEVICE_DT, DEVICE_DB = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -64,6 +67,7 @@ class DtrCfg(ctypes.Structure):
         ("order_seed", ctypes.c_uint64),
         ("check_adjacency", ctypes.c_int32),
         ("origin_mode", ctypes.c_int32),
+        ("device", ctypes.c_int32),
     ]
 
 
@@ -203,7 +207,8 @@ def seq_rs_roughness(L: int, p: float, q: float, times, seed: int, n: int, worke
 # --------------------------------------------------------------------------- DTr emulation
 @dataclass
 class Emu:
-    """Parameters of the DTr emulation (device DTr + block DT/DB/DTr)."""
+    """Parameters of the DTr emulation (device DTr + block DT/DB/DTr; device
+    dead border with ``device=DEVICE_DB``)."""
 
     L: int
     Dx: int
@@ -219,12 +224,13 @@ class Emu:
     order_seed: int = 0
     check_adjacency: bool = False
     origin_mode: int = ORIGIN_RANDOM
+    device: int = DEVICE_DT
 
     def cfg(self, window=None) -> DtrCfg:
         wx0, wy0, W, H = window if window is not None else (0, 0, self.L, self.L)
         return DtrCfg(self.L, self.Dx, self.Dy, self.Cx, self.Cy, self.scheme, self.seed,
                       self.stream, float(self.p), float(self.q), wx0, wy0, W, H, self.order,
-                      self.order_seed, int(self.check_adjacency), self.origin_mode)
+                      self.order_seed, int(self.check_adjacency), self.origin_mode, self.device)
 
     def validate(self) -> bool:
         c = self.cfg()

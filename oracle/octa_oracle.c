@@ -26,7 +26,9 @@
  *   4. Step-by-step emulation of DTr at device level (Sec. 3, DTr) with
  *      single-hit DT / DB (delayed borders) / DTr at block level (Sec. 3.1),
  *      under the counter-based random-number contract described at
- *      dtr_lane_draw() below.  Optional window mode for sampled checks.
+ *      dtr_lane_draw() below; the negative controls: a fixed or coarse
+ *      origin, and dead borders at device level (Sec. 3 DB, cDB of
+ *      Sec. 4.1).  Optional window mode for sampled checks.
  *   5. Heights and exact integer moments for W^2 (Sec. 2.1, roughness
  *      definition), the height autocorrelation C_h and the slope
  *      autocorrelation C_s (Sec. 2.1).
@@ -230,6 +232,9 @@ int64_t orc_seq_mcs(uint8_t *s, uint32_t L, uint64_t n_mcs, double p, double q, 
 /* ------------------------------------------------------------------------ */
 enum { ORC_DT = 0, ORC_DB = 1, ORC_DTR = 2 };
 enum { ORC_ORIGIN_RANDOM = 0, ORC_ORIGIN_FIXED = 1, ORC_ORIGIN_COARSE = 2 };
+/* device layer: double tiling (four domain sets per MCS; DTr with a random
+ * origin) or dead border (Sec. 3 DB: every tile at once, its rim inactive) */
+enum { ORC_DEVICE_DT = 0, ORC_DEVICE_DB = 1 };
 
 typedef struct {
     uint32_t L;        /* lateral size, power of two                        */
@@ -245,6 +250,7 @@ typedef struct {
     uint64_t order_seed;
     int32_t check_adjacency; /* 1: fail if two same-phase attempts touch   */
     int32_t origin_mode;     /* ORC_ORIGIN_*: random (DTr), fixed (DT), 4x4 grid */
+    int32_t device;          /* ORC_DEVICE_*: double tiling or dead border      */
 } orc_dtr_cfg;
 
 static int is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
@@ -267,7 +273,10 @@ int orc_dtr_validate(const orc_dtr_cfg *cfg)
 {
     if (!is_pow2(cfg->L) || cfg->L < 4) return -1;
     if (!is_pow2(cfg->Dx) || !is_pow2(cfg->Dy) || cfg->Dx < 2 || cfg->Dy < 2) return -1;
-    if (2 * cfg->Dx > cfg->L || 2 * cfg->Dy > cfg->L) return -1;
+    if (cfg->device != ORC_DEVICE_DT && cfg->device != ORC_DEVICE_DB) return -1;
+    /* double tiling: tiles of 2Dx x 2Dy; dead border: tiles of Dx x Dy */
+    if (cfg->device == ORC_DEVICE_DT && (2 * cfg->Dx > cfg->L || 2 * cfg->Dy > cfg->L)) return -1;
+    if (cfg->Dx > cfg->L || cfg->Dy > cfg->L) return -1;
     if (!is_pow2(cfg->Cx) || !is_pow2(cfg->Cy) || cfg->Cx < 2 || cfg->Cy < 2) return -1;
     if (cfg->Cx > 64 || cfg->Cy > 64 || cfg->Cx > cfg->Dx || cfg->Cy > cfg->Dy) return -1;
     if (cfg->scheme < ORC_DT || cfg->scheme > ORC_DTR) return -1;
@@ -490,6 +499,9 @@ static int64_t sweep_domain(uint8_t *s, const orc_dtr_cfg *cfg, const lane_shape
                             attempt_rec *rec, uint32_t *order, int32_t *stamp, int32_t *stamp_ctr,
                             uint32_t *hits, uint64_t *rs)
 {
+    /* dead border at device level: the domain's last column and last row
+     * are inactive; an attempt drawn there is not carried out (Sec. 3 DB) */
+    const int dead_rim = cfg->device == ORC_DEVICE_DB;
     const uint32_t ncx = cfg->Dx / cfg->Cx, ncy = cfg->Dy / cfg->Cy;
     const uint32_t ncell = ncx * ncy, rounds = cfg->Cx * cfg->Cy;
     int64_t attempts = 0;
@@ -515,6 +527,10 @@ static int64_t sweep_domain(uint8_t *s, const orc_dtr_cfg *cfg, const lane_shape
             rec[c].phase = cfg->scheme == ORC_DB
                                ? (int)(du == cfg->Cx - 1) + (int)(dv == cfg->Cy - 1)
                                : 0;
+            if (dead_rim && (u == cfg->Dx - 1 || v == cfg->Dy - 1)) {
+                rec[c].phase = 3; /* never carried out, but drawn */
+                ++attempts;
+            }
             rec[c].dep_ok = dep_ok;
             rec[c].rem_ok = rem_ok;
         }
@@ -558,10 +574,19 @@ static int64_t sweep_domain(uint8_t *s, const orc_dtr_cfg *cfg, const lane_shape
  * domain starts at (ox + 2Dx tx + a Dx, oy + 2Dy ty + b Dy) mod L, where
  * (a,b) = (set & 1, set >> 1).
  *
+ * Dead border at device level (cfg->device = ORC_DEVICE_DB; Sec. 3 DB, with
+ * origin_mode COARSE the paper's cDB): one step, k = 0, in which every tile
+ * of Dx x Dy sites, t = ty*(L/Dx) + tx starting at (ox + Dx tx, oy + Dy ty)
+ * mod L, gets its sweep, attempts on its last column or last row not
+ * carried out.  An active site's update reads and writes slopes of itself
+ * and of its right and lower neighbours only, all inside its own tile, so
+ * the tiles are independent and their order is irrelevant.  The set
+ * permutation is drawn but unused.
+ *
  * s: window state (W*H bytes).  valid: per-site validity flags for window
  * mode (NULL for the whole lattice).  stamp: W*H int32 scratch for the
  * adjacency check (NULL to skip).  hits: W*H counters incremented at every
- * attempted site (NULL to skip).  Returns attempts made (L*L for the whole
+ * attempted site (NULL to skip).  Returns attempts drawn (L*L for the whole
  * lattice) or a negative error.
  */
 int64_t orc_dtr_mcs(uint8_t *s, uint8_t *valid, const orc_dtr_cfg *cfg, uint32_t m, int32_t *stamp,
@@ -571,7 +596,9 @@ int64_t orc_dtr_mcs(uint8_t *s, uint8_t *valid, const orc_dtr_cfg *cfg, uint32_t
     if (m >= (1u << 30)) return -1;
     if ((cfg->W < cfg->L || cfg->H < cfg->L) && !valid) return -1;
     const lane_shape ls = lane_shape_of(cfg);
-    const uint32_t ntx = cfg->L / (2 * cfg->Dx), nty = cfg->L / (2 * cfg->Dy);
+    const int dead = cfg->device == ORC_DEVICE_DB;
+    const uint32_t span = dead ? 1u : 2u, nsteps = dead ? 1u : 4u;
+    const uint32_t ntx = cfg->L / (span * cfg->Dx), nty = cfg->L / (span * cfg->Dy);
     const uint32_t ncell = (cfg->Dx / cfg->Cx) * (cfg->Dy / cfg->Cy);
     attempt_rec *rec = (attempt_rec *)malloc(sizeof(attempt_rec) * ncell);
     uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
@@ -586,14 +613,14 @@ int64_t orc_dtr_mcs(uint8_t *s, uint8_t *valid, const orc_dtr_cfg *cfg, uint32_t
     uint32_t draw[6];
     orc_mcs_draw(cfg, m, draw);
     int64_t total = 0;
-    for (uint32_t k = 0; k < 4; ++k) {
-        uint32_t set = draw[2 + k], a = set & 1u, b = set >> 1;
+    for (uint32_t k = 0; k < nsteps; ++k) {
+        uint32_t set = dead ? 0u : draw[2 + k], a = set & 1u, b = set >> 1;
         for (uint32_t i = 0; i < ntx * nty; ++i) tiles[i] = cfg->order == 1 ? ntx * nty - 1 - i : i;
         if (cfg->order == 2) shuffle_u32(tiles, ntx * nty, &rs);
         for (uint32_t i = 0; i < ntx * nty; ++i) {
             uint32_t t = tiles[i], tx = t % ntx, ty = t / ntx;
-            uint32_t X0 = (draw[0] + 2 * cfg->Dx * tx + a * cfg->Dx) % cfg->L;
-            uint32_t Y0 = (draw[1] + 2 * cfg->Dy * ty + b * cfg->Dy) % cfg->L;
+            uint32_t X0 = (draw[0] + span * cfg->Dx * tx + a * cfg->Dx) % cfg->L;
+            uint32_t Y0 = (draw[1] + span * cfg->Dy * ty + b * cfg->Dy) % cfg->L;
             if (!footprint_ok(cfg, valid, X0, Y0)) continue;
             int64_t n = sweep_domain(s, cfg, &ls, m, k, t, X0, Y0, rec, order,
                                      cfg->check_adjacency ? stamp : NULL, &stamp_ctr, hits, &rs);
