@@ -65,17 +65,24 @@ extern "C" {
 #define OKPZ_BLOCK_DB 1  /* single-hit dead border, delayed borders, random cell origin per round */
 #define OKPZ_BLOCK_DTR 2 /* single-hit DT with the cell origin re-drawn per round */
 
-/* device-level origin of the double tiling */
+/* device-level origin of the decomposition */
 #define OKPZ_ORIGIN_RANDOM 0 /* DTr: uniform over all sites every MCS (Sec. 3, DTr)     */
 #define OKPZ_ORIGIN_FIXED 1  /* plain DT: origin stays at (0,0) (negative control)      */
-#define OKPZ_ORIGIN_COARSE 2 /* origin on the 4x4-site word grid (cDB-like control)     */
+#define OKPZ_ORIGIN_COARSE 2 /* origin on the 4x4-site word grid (cDB with _DEVICE_DB)  */
+
+/* device-level decomposition (Sec. 3) */
+#define OKPZ_DEVICE_DT 0 /* double tiling: four domain sets, four steps per MCS (DTr) */
+#define OKPZ_DEVICE_DB 1 /* dead border: every dom_x x dom_y tile in one step per MCS,
+                            its last column and last row inactive (negative control) */
 
 /*
  * Simulation parameters.  Physics parameters (Sec. 3.1 notation DTrDT etc.
  * and TC=log2(cell_x/4),log2(cell_y/4)):
  *   L             lateral size, power of two, 64 <= L <= 2^17
  *   dom_x, dom_y  device domain (sub-tile) size in sites; tiles are
- *                 2*dom_x x 2*dom_y.  Powers of two, >= 4, 2*dom <= L; the
+ *                 2*dom_x x 2*dom_y (dead border: dom_x x dom_y, the whole
+ *                 tile active but for its last column and row).  Powers of
+ *                 two, >= 4, 2*dom <= L; the
  *                 staged window, two bit planes of (dom_y + 4) rows by
  *                 (dom_x/32 + 3) words (plus 8 bytes per cell for DB), must
  *                 fit 160 KiB of LDS (dom_x <= 7936).
@@ -85,6 +92,12 @@ extern "C" {
  *   block_scheme  OKPZ_BLOCK_DT / _DB / _DTR
  *   seed, stream  Philox key; one stream per independent realization
  *   origin_mode   OKPZ_ORIGIN_RANDOM (the method) or a negative control
+ *   device_layer  OKPZ_DEVICE_DT (the method) or OKPZ_DEVICE_DB, the dead
+ *                 border control (with OKPZ_ORIGIN_COARSE the paper's cDB,
+ *                 Sec. 4.1): one step per MCS over all tiles, counter
+ *                 c3 = 4 MCS; an attempt drawn on a tile's last column or
+ *                 row is not carried out.  Single lattices only (batches and
+ *                 the server reject it).
  */
 typedef struct okpz_params {
     uint32_t L;
@@ -94,7 +107,7 @@ typedef struct okpz_params {
     uint32_t seed;
     uint32_t stream;
     int32_t origin_mode;
-    uint32_t reserved; /* must be 0 */
+    uint32_t device_layer; /* OKPZ_DEVICE_DT or OKPZ_DEVICE_DB */
 } okpz_params;
 
 /* 128-bit two's-complement integer: value = hi * 2^64 + lo */

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libokpz.so")
 OK, EINVAL, ENOMEM, EHIP, EOVERFLOW, ESTATE, EWAIT = 0, -1, -2, -3, -4, -5, -6
 BLOCK_DT, BLOCK_DB, BLOCK_DTR = 0, 1, 2
 ORIGIN_RANDOM, ORIGIN_FIXED, ORIGIN_COARSE = 0, 1, 2
+DEVICE_DT, DEVICE_DB = 0, 1
 SCHEMES = {"DT": BLOCK_DT, "DB": BLOCK_DB, "DTR": BLOCK_DTR, "DTr": BLOCK_DTR}
 
 
@@ -47,7 +48,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint32),
         ("stream", ctypes.c_uint32),
         ("origin_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_uint32),
+        ("device_layer", ctypes.c_uint32),
     ]
 
 
@@ -243,10 +244,11 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def params(L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0, origin_mode=ORIGIN_RANDOM) -> Params:
+def params(L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0, origin_mode=ORIGIN_RANDOM,
+           device_layer=DEVICE_DT) -> Params:
     if isinstance(scheme, str):
         scheme = SCHEMES[scheme]
-    return Params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode, 0)
+    return Params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode, device_layer)
 
 
 def validate(prm: Params) -> int:
@@ -263,9 +265,9 @@ class Lattice:
     """One octahedron-model lattice resident on the GPU."""
 
     def __init__(self, L, Dx, Dy, Cx, Cy, scheme=BLOCK_DT, seed=1, stream=0,
-                 origin_mode=ORIGIN_RANDOM, hip_stream=None, device_buffer=None):
+                 origin_mode=ORIGIN_RANDOM, hip_stream=None, device_buffer=None, device_layer=DEVICE_DT):
         lib = load()
-        self.prm = params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode)
+        self.prm = params(L, Dx, Dy, Cx, Cy, scheme, seed, stream, origin_mode, device_layer)
         self.L = L
         h = ctypes.c_void_p()
         s = ctypes.c_void_p(hip_stream) if hip_stream else None

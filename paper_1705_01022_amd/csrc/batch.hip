@@ -620,6 +620,8 @@ int okpz_batch_add(okpz_batch *b, okpz_lattice *lat, int32_t *slot)
     if (!b || !lat || !slot) return OKPZ_EINVAL;
     if (lat->stream != b->stream) return OKPZ_EINVAL;
     if (b->scheme >= 0 && lat->prm.block_scheme != b->scheme) return OKPZ_EINVAL;
+    if (lat->prm.device_layer != OKPZ_DEVICE_DT)
+        return fail_with(OKPZ_EINVAL, "okpz_batch_add: the dead-border control runs on single lattices only");
     for (okpz_lattice *m : b->slots)
         if (m == lat) return OKPZ_EINVAL;
     int32_t s = -1;

@@ -106,7 +106,8 @@ inline uint64_t step_lds_bytes(const okpz_params &p, uint32_t nslot = 0)
 {
     const WindowShape w = window_shape(p);
     if (nslot == 0) nslot = std::max<uint32_t>(cells_of(p), 256u);
-    return 4ull * step_lds_words(w.NR, w.P, w.NWX, w.PY, w.NB, w.shared_edges, nslot, p.block_scheme == OKPZ_BLOCK_DB);
+    return 4ull * step_lds_words(w.NR, w.P, w.NWX, w.PY, w.NB, w.shared_edges, nslot, p.block_scheme == OKPZ_BLOCK_DB,
+                                 p.device_layer == OKPZ_DEVICE_DB ? 1u : 0u);
 }
 
 inline int check_params(const okpz_params *p)
@@ -119,7 +120,7 @@ inline int check_params(const okpz_params *p)
     if (p->cell_x > 64 || p->cell_y > 64 || p->cell_x > p->dom_x || p->cell_y > p->dom_y) return OKPZ_EINVAL;
     if (p->block_scheme < OKPZ_BLOCK_DT || p->block_scheme > OKPZ_BLOCK_DTR) return OKPZ_EINVAL;
     if (p->origin_mode < OKPZ_ORIGIN_RANDOM || p->origin_mode > OKPZ_ORIGIN_COARSE) return OKPZ_EINVAL;
-    if (p->reserved != 0) return OKPZ_EINVAL;
+    if (p->device_layer != OKPZ_DEVICE_DT && p->device_layer != OKPZ_DEVICE_DB) return OKPZ_EINVAL;
     if (step_lds_bytes(*p) > kMaxLds) return OKPZ_EINVAL;
     const uint64_t ncell = uint64_t(p->dom_x / p->cell_x) * (p->dom_y / p->cell_y);
     if (ncell > 4096u) return OKPZ_EINVAL;  // at most 16 cells per lane of a 256-thread workgroup
@@ -275,7 +276,8 @@ inline StepArgs base_args(const okpz_lattice *lat, const LaneShape &ls, double p
     a.log2Cy = ilog2(p.cell_y);
     a.log2ncx = ilog2(p.dom_x / p.cell_x);
     a.ncell = (p.dom_x / p.cell_x) * (p.dom_y / p.cell_y);
-    a.log2ntx = ilog2(p.L / (2 * p.dom_x));
+    a.dev_db = p.device_layer == OKPZ_DEVICE_DB ? 1u : 0u;
+    a.log2ntx = ilog2(p.L / ((2 - a.dev_db) * p.dom_x));
     a.key0 = p.seed;
     a.key1 = p.stream;
     a.s_bits = ls.s_bits;

@@ -79,6 +79,8 @@ struct StepArgs {
     uint32_t flip_table;        // no acceptance draw: kFlipMin / kFlipMax for the patterns that flip
     uint32_t P_hi, P_lo, Q_hi, Q_lo;  // acceptance thresholds on the (A+32)-bit variate
     int32_t pq_delta;           // P_hi - Q_hi (row-paired DB kernel)
+    uint32_t dev_db;            // dead border at device level: every Dx x Dy tile in one step,
+                                // attempts on its last column / row not carried out
 };
 
 
@@ -105,8 +107,12 @@ __device__ __forceinline__ void copy_window(const StepArgs &A, uint32_t *lds, ui
             const uint32_t k = t >> 3, wib = t & 7u, row = 4u * b + (wib & 3u);
             const uint64_t g = ((band + ((bx0 + k) & A.nbx_mask)) << 3) + wib;
             const uint32_t li = wib < 4u ? row * A.P + k : sy_base + k * A.PY + row;
-            const bool edge = A.shared_edges && (k == 0 || k == A.NWX - 1);
-            const uint32_t oi = (b * 2u + (k == 0 ? 0u : 1u)) * 8u + wib;
+            // dead border: the tiles of one launch border each other, so the
+            // blocks of the first and last two columns and bands -- which
+            // may hold a neighbour's sites -- go back as XORs of the change
+            const bool edge = A.dev_db ? (k == 0 || k + 2u >= A.NWX || b == 0 || b + 2u >= A.NB)
+                                       : A.shared_edges && (k == 0 || k == A.NWX - 1);
+            const uint32_t oi = A.dev_db ? (b * A.NWX + k) * 8u + wib : (b * 2u + (k == 0 ? 0u : 1u)) * 8u + wib;
             if (LOAD) {
                 const uint32_t v = A.words[g];
                 lds[li] = v;
@@ -234,6 +240,8 @@ __device__ __forceinline__ Draw decode(const StepArgs &A, uint32_t field, uint32
     }
     d.sh = lx & 31u;
     d.mask = ACCEPT ? field >> A.s_bits : A.flip_table;  // acceptance prefix until accept_draws()
+    if (A.dev_db && (u == A.Dx - 1u || v == A.Dy - 1u))
+        d.mask = ACCEPT ? 0xFFFFFFFFu : 0u;  // dead border: a prefix no threshold accepts
     d.pos = SCHEME == kDB ? u | (v << 16) : 0u;
     d.rim = SCHEME == kDB ? ((du == (1u << A.log2Cx) - 1u) ? 1u : 0u) | ((dv == (1u << A.log2Cy) - 1u) ? 2u : 0u)
                           : 0u;
@@ -263,6 +271,9 @@ __device__ __forceinline__ CDraw decode_db(const StepArgs &A, uint32_t field, ui
     CDraw c;
     c.pos = u | (v << 16);
     c.ur = (ACCEPT ? (field >> A.s_bits) << 2 : 0u) | (du == cxm ? 1u : 0u) | (dv == cym ? 2u : 0u);
+    // dead border at device level: no threshold accepts the prefix; without
+    // acceptance draws bit 2 marks the attempt void for expand()
+    if (A.dev_db && (u == A.Dx - 1u || v == A.Dy - 1u)) c.ur = (ACCEPT ? 0xFFFFFFFCu : 4u) | (c.ur & 3u);
     return c;
 }
 
@@ -310,7 +321,7 @@ __device__ __forceinline__ Draw expand(const StepArgs &A, const CDraw &c, uint32
     d.ix = __umul24(ly, A.P << 2) + ((lx >> 3) & ~3u);
     d.iy = ((A.NR * A.P) << 2) + __umul24(lx >> 5, A.PY << 2) + (ly << 2);
     d.sh = lx & 31u;
-    d.mask = ACCEPT ? c.ur & ~3u : A.flip_table;
+    d.mask = ACCEPT ? c.ur & ~3u : ((c.ur & 4u) ? 0u : A.flip_table);
     d.pos = c.pos;
     d.rim = c.ur & 3u;
     return d;
@@ -481,10 +492,17 @@ __device__ __forceinline__ void db_round(const StepArgs &A, uint32_t *lds, uint3
 
 // LDS words of one device-step workgroup (see sweep_tile); nslot = lanes x
 // cells per lane.
-__host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint32_t NWX, uint32_t PY, uint32_t NB,
-                                                   uint32_t shared_edges, uint32_t nslot, bool db)
+// Words of the loaded copy kept for XOR write-back: two edge blocks per band
+// for narrow domains, every block under a dead border at device level.
+__host__ __device__ inline uint32_t orig_words(uint32_t NWX, uint32_t NB, uint32_t shared_edges, uint32_t dev_db)
 {
-    return NR * P + (NWX + 1u) * PY + (shared_edges ? 16u * NB : 0u) + (db ? 2u * nslot + 4u : 0u);
+    return dev_db ? 8u * NWX * NB : (shared_edges ? 16u * NB : 0u);
+}
+
+__host__ __device__ inline uint32_t step_lds_words(uint32_t NR, uint32_t P, uint32_t NWX, uint32_t PY, uint32_t NB,
+                                                   uint32_t shared_edges, uint32_t nslot, bool db, uint32_t dev_db)
+{
+    return NR * P + (NWX + 1u) * PY + orig_words(NWX, NB, shared_edges, dev_db) + (db ? 2u * nslot + 4u : 0u);
 }
 
 // One domain sweep (device step of one tile).  The tile's active domain
@@ -514,12 +532,13 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &A, uint32_t *smem, ui
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     uint32_t *lds = smem;                                              // sx plane, then sy plane
     uint32_t *orig = smem + A.NR * A.P + (A.NWX + 1u) * A.PY;          // edge blocks as loaded
-    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // DB: 2 x NT*CPT published sites
+    uint32_t *cpos = orig + orig_words(A.NWX, A.NB, A.shared_edges, A.dev_db);  // DB: 2 x NT*CPT published sites
     uint32_t *flags = cpos + 2u * NT * CPT;                            // DB: 3 round flags
 
     const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
-    const uint32_t X0 = (A.ox + 2u * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
-    const uint32_t Y0 = (A.oy + 2u * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
+    // tiles of 2D x 2D (double tiling) or D x D (dead border, one step per MCS)
+    const uint32_t X0 = (A.ox + (2u - A.dev_db) * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
+    const uint32_t Y0 = (A.oy + (2u - A.dev_db) * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
     const uint32_t offx = X0 & 31u, offy = Y0 & 3u;
 
     copy_window<true>(A, lds, orig, X0 >> 5, Y0 >> 2);
@@ -762,12 +781,13 @@ __device__ __forceinline__ void sweep_db_columns(const StepArgs &A, uint32_t *sm
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
     uint32_t *lds = smem;                                              // sx plane, then sy plane
     uint32_t *orig = smem + A.NR * A.P + (A.NWX + 1u) * A.PY;          // edge blocks as loaded
-    uint32_t *cpos = orig + (A.shared_edges ? 16u * A.NB : 0u);        // 2 x NT published top-cell sites
+    uint32_t *cpos = orig + orig_words(A.NWX, A.NB, A.shared_edges, A.dev_db);  // 2 x NT published top-cell sites
     uint32_t *flags = cpos + 2u * NT;                                  // 3 round flags
 
     const uint32_t tx = tile & ((1u << A.log2ntx) - 1u), ty = tile >> A.log2ntx;
-    const uint32_t X0 = (A.ox + 2u * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
-    const uint32_t Y0 = (A.oy + 2u * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
+    // tiles of 2D x 2D (double tiling) or D x D (dead border, one step per MCS)
+    const uint32_t X0 = (A.ox + (2u - A.dev_db) * A.Dx * tx + A.set_a * A.Dx) & A.L_mask;
+    const uint32_t Y0 = (A.oy + (2u - A.dev_db) * A.Dy * ty + A.set_b * A.Dy) & A.L_mask;
     const uint32_t offx = X0 & 31u, offy = Y0 & 3u;
 
     copy_window<true>(A, lds, orig, X0 >> 5, Y0 >> 2);

@@ -110,6 +110,9 @@ bool launch_dt_rows(uint32_t nt, uint32_t ntiles, hipStream_t st, const StepArgs
 template <int SCHEME, bool ACCEPT, int CPT>
 int launch_step_inst(uint32_t nt, uint32_t ntiles, size_t lds, hipStream_t st, const StepArgs &a)
 {
+    // the dead-border control runs the generic kernel (the only one that
+    // masks the tiles' rims and XORs back the words they share)
+    if (a.dev_db) return launch_instance(&step_kernel<SCHEME, ACCEPT, CPT>, nt, ntiles, lds, st, a);
     if constexpr (SCHEME != kDB) {
         int rc = OKPZ_OK;
         if (launch_dt_rows<SCHEME, ACCEPT, CPT>(nt, ntiles, st, a, rc)) return rc;
@@ -150,7 +153,8 @@ int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
 {
     const okpz_params &p = lat->prm;
     const uint32_t ncell = a.ncell;
-    const uint32_t ntiles = (p.L / (2 * p.dom_x)) * (p.L / (2 * p.dom_y));
+    const uint32_t span = a.dev_db ? 1u : 2u;  // dead border: every dom_x x dom_y tile in one step
+    const uint32_t ntiles = (p.L / (span * p.dom_x)) * (p.L / (span * p.dom_y));
     uint32_t cpt, nt;
     step_shape(ncell, lat->threads ? lat->threads : default_threads(ntiles, lat->cus), cpt, nt);
     if (cpt > 16) return OKPZ_EINVAL;
@@ -494,9 +498,12 @@ int okpz_run(okpz_lattice *lat, uint64_t n_mcs, double p, double q)
         const McsDraw d = mcs_draw(lat->prm, m);
         a.ox = d.ox;
         a.oy = d.oy;
-        for (uint32_t k = 0; k < 4; ++k) {
-            a.set_a = (uint32_t)d.perm[k] & 1u;
-            a.set_b = (uint32_t)d.perm[k] >> 1;
+        // double tiling: the four domain sets in the drawn order; dead border:
+        // one step over all tiles (counter 4 MCS + 0)
+        const uint32_t nsteps = a.dev_db ? 1u : 4u;
+        for (uint32_t k = 0; k < nsteps; ++k) {
+            a.set_a = a.dev_db ? 0u : (uint32_t)d.perm[k] & 1u;
+            a.set_b = a.dev_db ? 0u : (uint32_t)d.perm[k] >> 1;
             a.c3 = (uint32_t)(m << 2) | k;
             TimedPair tp;
             begin_timed(lat, 0, tp);

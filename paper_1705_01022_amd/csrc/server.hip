@@ -278,6 +278,8 @@ int okpz_server_submit(okpz_server *s, const okpz_params *prm, uint64_t n_mcs, d
     if (!s || !prm || !id) return OKPZ_EINVAL;
     const int rc = check_params(prm);
     if (rc != OKPZ_OK) return rc;
+    if (prm->device_layer != OKPZ_DEVICE_DT)
+        return fail_with(OKPZ_EINVAL, "okpz_server_submit: the dead-border control runs on single lattices only");
     if (n_mcs == 0 || n_mcs > kMcsLimit) return OKPZ_EINVAL;
     if (!(p >= 0.0 && p <= 1.0 && q >= 0.0 && q <= 1.0)) return OKPZ_EINVAL;
     if (footprint(*prm) > s->cfg.hbm_budget) return OKPZ_ENOMEM;

@@ -104,6 +104,12 @@ def test_validate(okpz, prm, ok):
         assert r == okpz.EINVAL
 
 
+@pytest.mark.parametrize("layer,ok", [(0, True), (1, True), (2, False), (0xFFFFFFFF, False)])
+def test_validate_device_layer(okpz, layer, ok):
+    p = okpz.params(256, 32, 32, 8, 8, 1, device_layer=layer)
+    assert (okpz.validate(p) == 256 * 256 // 4) == ok
+
+
 def test_missing_library_fails_loudly(monkeypatch, okpz):
     import importlib
     import paper_1705_01022_amd as pkg
