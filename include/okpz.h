@@ -207,8 +207,9 @@ int okpz_init_from_host(okpz_lattice *lat, const uint8_t *sites, uint64_t mcs);
  * Advance n_mcs Monte Carlo steps at deposition probability p and removal
  * probability q (0 <= p, q <= 1; Sec. 2.1 rule).  Each MCS draws a fresh
  * random tiling origin and an order of the four domain sets and sweeps them
- * (Sec. 3, DTr).  Asynchronous on the handle's stream.  OKPZ_EOVERFLOW if the
- * MCS counter would reach 2^30.
+ * (Sec. 3, DTr); with device_layer OKPZ_DEVICE_DB it sweeps every tile in one
+ * step instead, their rims inactive (Sec. 3 DB).  Asynchronous on the
+ * handle's stream.  OKPZ_EOVERFLOW if the MCS counter would reach 2^30.
  */
 int okpz_run(okpz_lattice *lat, uint64_t n_mcs, double p, double q);
 
