@@ -70,3 +70,40 @@ def test_dead_border_rejected_by_batches(okpz):
         b.add(lat)  # the same lattice with double tiling joins
         b.remove(lat.slot)
     b.close()
+
+
+def _slope_ac(okpz, L, D, origin, n, s, ratios):
+    """Mean and SE of C_s(t, s) over n single lattices (streams 0 .. n-1) of
+    the dead-border layer with block DT at p = 1, at t = s * ratio."""
+    lats = [okpz.Lattice(L, D, D, 8, 8, okpz.BLOCK_DT, 3, r, origin_mode=origin, device_layer=okpz.DEVICE_DB)
+            for r in range(n)]
+    try:
+        for lat in lats:
+            lat.run(s, 1.0, 0.0)
+            lat.snapshot()
+        out, t = [], s
+        for rr in ratios:
+            for lat in lats:
+                lat.run(s * rr - t, 1.0, 0.0)
+            t = s * rr
+            cs = np.array([lat.observe(True)[1]["c_s"] for lat in lats])
+            out.append((cs.mean(), cs.std(ddof=1) / np.sqrt(n)))
+            print("dead border origin=%d L=%d t/s=%d C_s=%.3e +- %.1e" % (origin, L, rr, *out[-1]), flush=True)
+        return out
+    finally:
+        for lat in lats:
+            lat.close()
+
+
+def test_coarse_dead_border_imprints_a_slope_pattern(okpz):
+    """The paper's cDB artifact (Sec. 4.1): with the origin on the 4x4 grid
+    only sites with x or y = 3 (mod 4) are ever dead, and the slope
+    autocorrelation stops decaying at a finite value; a freely moving origin
+    removes it.  L = 4096, D = 64, 128 lattices per origin, s = 100 MCS."""
+    L, D, n, s = 4096, 64, 128, 100
+    cdb = _slope_ac(okpz, L, D, okpz.ORIGIN_COARSE, n, s, [10, 20])
+    dbr = _slope_ac(okpz, L, D, okpz.ORIGIN_RANDOM, n, s, [10, 20])
+    for (mc, ec), (mr, er) in zip(cdb, dbr):
+        assert mc - mr > 4.0 * np.hypot(ec, er), (mc, ec, mr, er)
+    # no decay between t/s = 10 and 20 (the random origin's C_s falls several-fold there)
+    assert cdb[1][0] > 0.6 * cdb[0][0]
