@@ -110,12 +110,12 @@ __device__ __forceinline__ u32x4 mcs_origin(const BatchSlot &S, uint64_t m, uint
 // 8 x 8-site cells, and each item runs the row-paired DT sweep for its
 // lattice's domain size and rates.
 //
-// DT and DTr with at most 4 cells per lane: six waves per SIMD (80 VGPRs and
-// 40 bytes spilled to scratch; the LDS allows seven workgroups per compute
-// unit) run the 512-realisation batch 5 % faster than the five that the
-// unconstrained 93 VGPRs allow.  The row-paired sweep runs two cells per
-// lane (75 VGPRs, six waves per SIMD): with four, the batch kernel's own state
-// on top of the sweep's pushes it into scratch spills.
+// DT and DTr with at most 4 cells per lane: six waves per SIMD (80 VGPRs;
+// the generic sweep spills 40 bytes to scratch for it and ran the
+// 512-realisation batch 5 % faster than the five waves its unconstrained 93
+// VGPRs allow; the row-paired DT sweep fits).  The row-paired DB sweep runs
+// two cells per lane (63 VGPRs): with four, the batch kernel's own state on
+// top of the sweep's needs 117 VGPRs (four waves), or spills at five.
 template <int SCHEME, int CPT, bool COLS, int FL, int LD>
 __global__ void __launch_bounds__(kMaxStepThreads)
 __attribute__((amdgpu_waves_per_eu((SCHEME != kDB && CPT <= 4) || LD > 0 ? 6 : 1)))
