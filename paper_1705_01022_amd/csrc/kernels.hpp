@@ -1129,16 +1129,21 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
         h0r[r] = h0[4 * band + r];
         if (CROSS) h0sr[r] = h0s[4 * band + r];
     }
-    int64_t lin_e = 0, lin_o = 0, quad_e = 0, quad_o = 0, xa = 0;
+    // |h| <= L on the periodic surface (gauge h(0,0) = 0), so a lane's sums of
+    // 16 A + sum q over its at most 4 L/64 block rows stay below 2^31
+    int32_t lin_e = 0, lin_o = 0;
+    int64_t quad_e = 0, quad_o = 0, xa = 0;
     uint32_t u2 = 0, u2e = 0, ue = 0, uall = 0, us_all = 0, uts = 0;
     uint32_t rows = 0;      // block rows this lane took part in
     uint32_t overlap = 0;   // at most 8 L per band
     // one chunk of 64 blocks; FIRST: the band's first chunk, whose lane 0
     // holds the lattice's first block (site 0 without a step)
-    auto chunk = [&](uint32_t base, auto first_c) {
+    // FULL: every lane of the chunk holds a block (bands of at least 64 blocks)
+    auto chunk = [&](uint32_t base, auto first_c, auto full_c) {
         constexpr bool FIRST = decltype(first_c)::value;
+        constexpr bool FULL = decltype(full_c)::value;
         const uint32_t bx = base + lane;
-        const bool active = bx < nbx;
+        const bool active = FULL || bx < nbx;
         uint4 wv = make_uint4(0, 0, 0, 0), sv = make_uint4(0, 0, 0, 0);
         if (active) {
             wv = *reinterpret_cast<const uint4 *>(words + band_base + 8u * bx);  // sx rows 0..3
@@ -1161,13 +1166,25 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
             int32_t Rs = 0;
             if (CROSS) Rs = row_offsets<r, false, FIRST>(lut, sk[r], Us, b2, b2e, sus, suse);
             if (!active) R = Rs = 0;  // lanes past the end of a short band add nothing
-            int32_t tot, tot_s = 0;
-            const int32_t ex = wave_excl_scan_i32(R, tot);
+            int32_t ex, tot, exs = 0, tot_s = 0;
+            if (CROSS) {
+                // both scans in one: R + 64 and Rs + 64 (R in [-32, 33]) in the
+                // two halves of a word, whose sums over 64 lanes stay below 2^16
+                const uint32_t pk = (uint32_t)(R + 64) | ((uint32_t)(Rs + 64) << 16);
+                int32_t totp;
+                const uint32_t exp = (uint32_t)wave_excl_scan_i32((int32_t)pk, totp);
+                const int32_t off = 64 * (int32_t)lane;
+                ex = (int32_t)(exp & 0xFFFFu) - off;
+                exs = (int32_t)(exp >> 16) - off;
+                tot = (int32_t)((uint32_t)totp & 0xFFFFu) - 4096;
+                tot_s = (int32_t)((uint32_t)totp >> 16) - 4096;
+            } else {
+                ex = wave_excl_scan_i32(R, tot);
+            }
             const int32_t A = h0r[r] + carry[r] + ex;  // height before the block
             carry[r] += tot;
             int32_t As = 0;
             if (CROSS) {
-                const int32_t exs = wave_excl_scan_i32(Rs, tot_s);
                 As = h0sr[r] + carry_s[r] + exs;
                 carry_s[r] += tot_s;
             }
@@ -1197,8 +1214,12 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
         one_row(std::integral_constant<int, 2>());
         one_row(std::integral_constant<int, 3>());
     };
-    chunk(0u, std::true_type());
-    for (uint32_t base = 64; base < nbx; base += 64) chunk(base, std::false_type());
+    if (nbx >= 64u) {  // nbx is a power of two: whole chunks only
+        chunk(0u, std::true_type(), std::true_type());
+        for (uint32_t base = 64; base < nbx; base += 64) chunk(base, std::false_type(), std::true_type());
+    } else {
+        chunk(0u, std::true_type(), std::false_type());
+    }
     // sums of q and q^2 from those of u = q + 64 (16 sites per class per block row)
     const int64_t n16 = 16 * (int64_t)rows;
     const int64_t uo = (int64_t)uall - ue, u2o = (int64_t)u2 - u2e;
