@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(kMeasureThreads) batch_rows_kernel(const Measu
                                                                      const uint32_t *band_prefix, uint32_t n,
                                                                      int64_t *__restrict__ partial)
 {
-    __shared__ __align__(8) uint32_t lut[512];
+    __shared__ __align__(8) uint32_t lut[kLutWords];
     build_tables(lut);
     __syncthreads();
     const uint32_t gb = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);

@@ -136,6 +136,14 @@ constexpr uint32_t kPatternMin = 0x9u, kPatternMax = 0x6u;
 constexpr uint32_t kFlipMin = (1u << kPatternMin) | (1u << (kPatternMin + 16u));
 constexpr uint32_t kFlipMax = (1u << kPatternMax) | (1u << (kPatternMax + 16u));
 
+// a + b + c in one instruction; c uniform.
+__device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 // a * b + c for a, b below 2^24 (one full-rate multiply-add); b uniform.
 __device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -1032,19 +1040,28 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
 
 constexpr int kMomentFields = 6;  // S1_even, S1_odd, S2_even, S2_odd, S_ts, slope overlap
 
-// Spread-prefix table of a byte b (8 sites, bit m = slope bit of site m),
-// two words per entry: byte m of word j = number of 1 bits among bits
-// 0 .. 4j + m.
+// Offset-byte tables of a byte b of a block row (8 sites, bit j = slope bit
+// of site j; P_j = number of 1 bits among bits 0 .. j), two words per entry,
+// byte j of the pair = the offset height of site j (see row_offsets):
+//   lut[2 b], lut[2 b + 1]               first byte of a row: 2 P_j + 63 - j
+//   lut[512 + 2 b], lut[512 + 2 b + 1]   later bytes: 2 P_j + 7 - j, the
+//                                        offsets relative to the previous
+//                                        byte's last one, plus 8
+constexpr uint32_t kLutWords = 1024;
+
 __device__ void build_tables(uint32_t *lut)
 {
     for (uint32_t b = threadIdx.x; b < 256; b += blockDim.x) {
-        uint32_t acc = 0, e[2] = {0u, 0u};
-        for (uint32_t m = 0; m < 8; ++m) {
-            acc += (b >> m) & 1u;
-            e[m >> 2] |= acc << (8 * (m & 3));
+        uint32_t acc = 0, first[2] = {0u, 0u}, rest[2] = {0u, 0u};
+        for (uint32_t j = 0; j < 8; ++j) {
+            acc += (b >> j) & 1u;
+            first[j >> 2] |= (2u * acc + 63u - j) << (8 * (j & 3));
+            rest[j >> 2] |= (2u * acc + 7u - j) << (8 * (j & 3));
         }
-        lut[2 * b] = e[0];
-        lut[2 * b + 1] = e[1];
+        lut[2 * b] = first[0];
+        lut[2 * b + 1] = first[1];
+        lut[512 + 2 * b] = rest[0];
+        lut[512 + 2 * b + 1] = rest[1];
     }
 }
 
@@ -1054,35 +1071,44 @@ constexpr int kMeasureThreads = 256;
 // multiple of 32).  Relative heights q_i = sum_{j <= i} (2 b_j - 1) (for the
 // lattice's first block site 0 has no step: b_0 is cleared and q_i =
 // sum_{1 <= j <= i} (2 b_j - 1)) are formed four at a time as offset bytes
-// u_i = q_i + 64 in [32, 96]: u = 2 P + (63 - i) (+1 in the first block) with
-// P_i the number of 1 bits among bits 0 .. i, from the byte's spread-prefix
-// table entry plus the count of the bytes before (broadcast to every byte).
-// Byte dot products then give sums of u and u^2 over all sites and over the
-// sites of one parity class (the class bytes of two nibbles gathered into
-// one word).  Returns q_31, the block's height change; U[k] keeps the bytes of
-// nibble k for a cross product.  MOM = false: only the sum of u over all
-// sites (what a snapshot row needs).  FIRST: the chunk holding the lattice's
-// first block, in lane 0 (the only lane that takes the first-block path).
+// u_i = q_i + 64 = 2 P_i + 63 - i in [32, 96] (+1 in the first block), P_i
+// the number of 1 bits among bits 0 .. i: the row's first byte straight from
+// its table entry, each later byte as its table entry (relative offsets + 8)
+// plus the previous byte's last offset broadcast to every byte, minus 8 --
+// one permute and two three-input adds per byte; no byte sum carries or
+// borrows.  Byte dot products then give sums of u and u^2 over all sites and
+// over the sites of one parity class (the class bytes of two nibbles
+// gathered into one word).  Returns q_31, the block's height change; U[k]
+// keeps the bytes of nibble k for a cross product.  MOM = false: only the
+// sum of u over all sites (what a snapshot row needs).  FIRST: the chunk
+// holding the lattice's first block, in lane 0 (the only lane that takes the
+// first-block path).
 template <int R, bool MOM, bool FIRST>
 __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, uint32_t (&U)[8], uint32_t &u2,
                                                uint32_t &u2e, uint32_t &su, uint32_t &sue)
 {
     const bool f = FIRST && (threadIdx.x & 63u) == 0u;
-    const uint32_t dl = f ? 0x01010101u : 0u;
     // parity class "even" (x + y even): even i on even rows, odd i on odd rows;
     // bytes (m, m + 2) of nibbles k and k + 1 (permute selectors: 0-3 pick bytes
     // of the second operand, 4-7 of the first)
     constexpr uint32_t sel = (R & 1) ? 0x07050301u : 0x06040200u;
     if (f) w &= ~1u;
-    uint32_t B = 0u, s2 = 0u, s2e = 0u, s1 = 0u, s1e = 0u;
+    uint32_t prev = 0u, s2 = 0u, s2e = 0u, s1 = 0u, s1e = 0u;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const uint32_t off = ((w >> (8 * m)) & 0xFFu) << 3;  // byte offset of the table entry
-        const uint2 e = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lut) + off);
-        const uint32_t pb0 = e.x + B, pb1 = e.y + B;
-        B = __builtin_amdgcn_perm(pb1, pb1, 0x07070707u);  // P_{8m+7} in every byte
-        const uint32_t c0 = (63u - 8u * (uint32_t)m) * 0x01010101u - 0x03020100u + dl;  // bytes 63 - i
-        const uint32_t u0 = (pb0 << 1) + c0, u1 = (pb1 << 1) + (c0 - 0x04040404u);
+        const uint2 e = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lut) + (m ? 2048u : 0u) + off);
+        uint32_t u0, u1;
+        if (m == 0) {
+            const uint32_t dl = f ? 0x01010101u : 0u;
+            u0 = e.x + dl;
+            u1 = e.y + dl;
+        } else {
+            const uint32_t bp = __builtin_amdgcn_perm(prev, prev, 0x07070707u);  // u_{8m-1} in every byte
+            u0 = add3(e.x, bp, 0u - 0x08080808u);
+            u1 = add3(e.y, bp, 0u - 0x08080808u);
+        }
+        prev = u1;
         U[2 * m] = u0;
         U[2 * m + 1] = u1;
         s1 = __builtin_amdgcn_udot4(u0, 0x01010101u, s1, false);
@@ -1099,7 +1125,7 @@ __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, 
     u2e += s2e;
     su = s1;
     sue = s1e;
-    return 2 * (int32_t)(B & 0xFFu) - 32 + (f ? 1 : 0);
+    return (int32_t)(prev >> 24) - 64;  // u_31 - 64 = q_31
 }
 
 // One wave: the moments of band `band` of one lattice into out[0..5].  Lane l
@@ -1254,7 +1280,7 @@ __global__ void __launch_bounds__(kMeasureThreads) rows_kernel(const uint32_t *_
                                                                const int32_t *__restrict__ h0s, uint32_t L,
                                                                uint32_t nbx_log2, int64_t *__restrict__ partial)
 {
-    __shared__ __align__(8) uint32_t lut[512];
+    __shared__ __align__(8) uint32_t lut[kLutWords];
     build_tables(lut);
     __syncthreads();
     const uint32_t band = blockIdx.x * (kMeasureThreads / 64) + (threadIdx.x >> 6);
