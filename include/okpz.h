@@ -313,7 +313,9 @@ int okpz_get_mcs(const okpz_lattice *lat, uint64_t *mcs);
 /*
  * Workgroup size of the device-step kernel: 64, 128, 256 or 512 threads, or
  * 0 for the default (512 when a device step has fewer tiles than four per
- * compute unit, else 256).  Each thread then updates ncell / threads thread
+ * compute unit, else 256; at most ncell / 2 when the domain has 256 thread
+ * cells or more, so that each thread holds two or more).  Each thread then
+ * updates ncell / threads thread
  * cells (at most 16, else OKPZ_EINVAL).  A physical mapping only: the simulated
  * lattice does not depend on it (every random draw is keyed by cell, not by
  * thread).  Chosen by an autotuner per domain shape.
@@ -391,7 +393,8 @@ int okpz_batch_size(const okpz_batch *batch, uint32_t *nslots);
  * Launch shape (physical mapping only; results do not depend on it):
  * threads per workgroup (64, 128, 256, 512, or 0: enough lanes for the
  * largest domain's cells, at most 256, or 512 when the launch has fewer
- * tiles per step than four per compute unit), persistent workgroups
+ * tiles per step than four per compute unit, and at most half the cells of
+ * a domain of 256 cells or more), persistent workgroups
  * (0 = as many as fit on the device at once, but no more than the members'
  * tiles in one step), use_graph (capture and replay the launch).  Chosen by
  * the autotuner of the Python layer.

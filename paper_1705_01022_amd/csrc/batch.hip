@@ -708,7 +708,8 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
     const uint32_t n = (uint32_t)order.size();
 
     // launch shape: lanes per workgroup (default: enough for the largest
-    // domain's cells, 64 .. 256), cells per lane
+    // domain's cells, 64 .. 256, at most half of them from 256 cells on),
+    // cells per lane
     uint32_t max_cells = 1;
     for (int32_t s : order) max_cells = std::max(max_cells, cells_of(b->slots[s]->prm));
     uint32_t nt = b->threads;
@@ -718,7 +719,7 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
         int dev = 0, cus = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const uint32_t cap = default_threads(tiles, (uint32_t)std::max(cus, 1));
+        const uint32_t cap = default_threads(tiles, (uint32_t)std::max(cus, 1), max_cells);
         nt = 64;
         while (nt < cap && nt < max_cells) nt *= 2;
     }

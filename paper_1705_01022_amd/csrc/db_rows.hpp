@@ -35,8 +35,8 @@ namespace okpz {
 
 // Compile-time geometry of a square D x D domain (LD = log2 D >= 5) with
 // C x C-site cells (LC = log2 C): the same window as window_shape() on the
-// host (NWX blocks, NB bands).
-template <int LD, int LC>
+// host (NWX blocks, NB bands).  WIDE: the DT / DTr step's row pitch (below).
+template <int LD, int LC, bool WIDE = false>
 struct RowPairShape {
     static constexpr uint32_t D = 1u << LD;
     static constexpr uint32_t C = 1u << LC;
@@ -48,11 +48,18 @@ struct RowPairShape {
     static constexpr uint32_t P = NWX | 1u;
     static constexpr uint32_t NB = D / 4 + 1;
     static constexpr uint32_t NR = 4 * NB;
-    // words per window row (sx words, sy words, one pad word): odd, so that
-    // rows 32 apart -- the two lane rows of a wave -- fall on different
-    // banks; 19 words at D = 256 keep the window and the published sites of
-    // 256 lanes within a seventh of the compute unit's LDS
-    static constexpr uint32_t PITCH = 2 * P + 1;
+    // words per window row (sx words, sy words, padding).  DB: 2P + 1, odd,
+    // so that rows 32 apart -- the two lane rows of a wave -- fall on
+    // different banks; 19 words at D = 256 keep the window and the published
+    // sites of 256 lanes within a seventh of the compute unit's LDS.  DT / DTr
+    // at D = 256 (WIDE): 24 words, which puts four consecutive rows on the
+    // bank offsets 0, 24, 16 and 8 of the 32 banks, so that the eight words
+    // of a row that the 32 lanes of a cell row reach, over the four rows of
+    // a quadrant, fall on distinct banks (the window then allows six
+    // workgroups per compute unit; the DB step, whose attempts span the eight
+    // rows of a cell, gains less from it than it loses with the seventh)
+    static constexpr uint32_t PITCH = (WIDE && LD == 8) ? 24u : 2 * P + 1;
+    static_assert(PITCH >= 2 * P + 1, "a row holds its sx and sy words");
     static constexpr uint32_t ROW = 32 * PITCH;      // bits per window row (linear site index stride)
     static constexpr uint32_t NCX = D / C;           // cells per domain row
     static constexpr uint32_t LOG2NCX = LD - LC;

@@ -14,11 +14,11 @@
 
 namespace okpz {
 
-// LDS words of the row-paired DT / DTr step: the window alone.
+// LDS words of the row-paired DT / DTr step: the window alone (wide rows).
 template <int LD, int LC>
 __host__ __device__ constexpr uint32_t rowpair_dt_lds_words()
 {
-    return RowPairShape<LD, LC>::WORDS;
+    return RowPairShape<LD, LC, true>::WORDS;
 }
 
 // Lane t holds the cells (t mod NCX, CPT (t / NCX) + j), j = 0 .. CPT-1,
@@ -28,7 +28,7 @@ __host__ __device__ constexpr uint32_t rowpair_dt_lds_words()
 template <int SCHEME, bool ACCEPT, int CPT, int LD, int LC>
 __device__ __forceinline__ void sweep_dt_rows(const StepArgs &A, uint32_t *smem, uint32_t tile)
 {
-    using S = RowPairShape<LD, LC>;
+    using S = RowPairShape<LD, LC, true>;
     constexpr int FL = ACCEPT ? 4 : 2;
     constexpr uint32_t F = 1u << FL;
     constexpr int RPB = 128 >> FL;             // rounds per Philox block

@@ -242,10 +242,14 @@ inline void end_timed(okpz_lattice *lat, TimedPair &tp)
 // the domain has fewer cells.  Results do not depend on the shape.
 // Lanes per device-step workgroup when none is configured: 256, or 512 when a
 // step has fewer than 4 tiles per compute unit (more lanes then share the few
-// tiles; with more tiles 256-lane workgroups keep more of them resident).
-inline uint32_t default_threads(uint64_t ntiles, uint32_t cus)
+// tiles; with more tiles 256-lane workgroups keep more of them resident);
+// at most half the domain's cells once it has 256 or more, so that every lane
+// holds two cells or more: the row-paired DB kernel needs two, and the other
+// kernels then pay one barrier per two attempts of a lane instead of one.
+inline uint32_t default_threads(uint64_t ntiles, uint32_t cus, uint32_t ncell)
 {
-    return ntiles < 4ull * cus ? 512u : 256u;
+    const uint32_t nt = ntiles < 4ull * cus ? 512u : 256u;
+    return ncell >= 256u ? std::min(nt, ncell / 2u) : nt;
 }
 
 inline void step_shape(uint32_t ncell, uint32_t threads, uint32_t &cpt, uint32_t &nt)

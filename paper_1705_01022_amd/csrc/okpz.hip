@@ -156,7 +156,7 @@ int launch_step(okpz_lattice *lat, const StepArgs &a, bool accept)
     const uint32_t span = a.dev_db ? 1u : 2u;  // dead border: every dom_x x dom_y tile in one step
     const uint32_t ntiles = (p.L / (span * p.dom_x)) * (p.L / (span * p.dom_y));
     uint32_t cpt, nt;
-    step_shape(ncell, lat->threads ? lat->threads : default_threads(ntiles, lat->cus), cpt, nt);
+    step_shape(ncell, lat->threads ? lat->threads : default_threads(ntiles, lat->cus, ncell), cpt, nt);
     if (cpt > 16) return OKPZ_EINVAL;
     const size_t lds = step_lds_bytes(p, nt * cpt);
     int rc;
