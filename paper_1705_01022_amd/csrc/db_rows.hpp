@@ -6,7 +6,7 @@
 //
 //  * Window layout.  Row r of the staged window keeps its sx words at
 //    r * W + k and its sy words at r * W + P + k (k = 0 .. NWX-1, block k of
-//    the window; row pitch W = 2P + 1 words), so the four slope words an
+//    the window; row pitch W >= 2P + 1 words), so the four slope words an
 //    attempt reads -- sx(x, y), sx(x+1, y), sy(x, y), sy(x, y+1) -- sit at
 //    one address plus the immediate offsets 0, 1, P and P + W words (two
 //    ds_read2 instructions, one address).  P, W and everything else sized by
@@ -48,17 +48,18 @@ struct RowPairShape {
     static constexpr uint32_t P = NWX | 1u;
     static constexpr uint32_t NB = D / 4 + 1;
     static constexpr uint32_t NR = 4 * NB;
-    // words per window row (sx words, sy words, padding).  DB: 2P + 1, odd,
-    // so that rows 32 apart -- the two lane rows of a wave -- fall on
-    // different banks; 19 words at D = 256 keep the window and the published
-    // sites of 256 lanes within a seventh of the compute unit's LDS.  DT / DTr
-    // at D = 256 (WIDE): 24 words, which puts four consecutive rows on the
-    // bank offsets 0, 24, 16 and 8 of the 32 banks, so that the eight words
-    // of a row that the 32 lanes of a cell row reach, over the four rows of
-    // a quadrant, fall on distinct banks (the window then allows six
-    // workgroups per compute unit; the DB step, whose attempts span the eight
-    // rows of a cell, gains less from it than it loses with the seventh)
-    static constexpr uint32_t PITCH = (WIDE && LD == 8) ? 24u : 2 * P + 1;
+    // words per window row (sx words, sy words, padding), chosen against LDS
+    // bank conflicts (32 banks; the 32 lanes of a half-wave hold one cell
+    // row): 2P + 1 below D = 256.  At D = 256, DT / DTr (WIDE): 24 words,
+    // which puts the four rows of a quadrant on the bank offsets 0, 24, 16
+    // and 8, so that the eight words a cell row's attempts reach in each of
+    // them fall on distinct banks (the window then leaves room for six
+    // workgroups per compute unit).  DB: 20 words, which spreads the eight
+    // rows of a cell over the bank offsets 0, 20, 8, 28, 16, 4, 24, 12, and
+    // keeps the window and the published sites of 256 lanes within a
+    // seventh of the compute unit's LDS (a 24-word pitch would cost DB the
+    // seventh workgroup, and more time than its fewer conflicts save).
+    static constexpr uint32_t PITCH = LD == 8 ? (WIDE ? 24u : 20u) : 2 * P + 1;
     static_assert(PITCH >= 2 * P + 1, "a row holds its sx and sy words");
     static constexpr uint32_t ROW = 32 * PITCH;      // bits per window row (linear site index stride)
     static constexpr uint32_t NCX = D / C;           // cells per domain row
