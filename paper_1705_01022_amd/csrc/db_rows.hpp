@@ -202,6 +202,21 @@ __device__ __forceinline__ void attempt_rows(const StepArgs &A, uint32_t s, uint
     }
 }
 
+// (du + cu) mod D, the column of a draw in the shifted cell grid; at D = 256
+// one byte-select add (the sum's low byte, the other bytes cleared).
+template <int LD>
+__device__ __forceinline__ uint32_t wrap_column(uint32_t du, uint32_t cu)
+{
+    if constexpr (LD == 8) {
+        uint32_t r;
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:BYTE_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+            : "=v"(r) : "v"(du), "v"(cu));
+        return r;
+    } else {
+        return (du + cu) & ((1u << LD) - 1u);
+    }
+}
+
 // Linear site of a DB lane draw: site (du, dv) = (field mod C, field / C mod
 // C) of the cell whose corner, with the round's cell-grid shift, is
 // (cu, cv) -- both wrap around the domain (Sec. 3.1 DB: the shifted cell grid
@@ -216,9 +231,22 @@ __device__ __forceinline__ uint32_t site_rows(uint32_t field, uint32_t cu, uint3
     using S = RowPairShape<LD, LC>;
     const uint32_t du = field & (S::C - 1u);
     const uint32_t dv = (field >> LC) & (S::C - 1u);
-    const uint32_t u = (du + cu) & (S::D - 1u);
+    const uint32_t u = wrap_column<LD>(du, cu);
     const uint32_t v = wrapv ? (dv + cv) & (S::D - 1u) : dv + cv;
     return __umul24(v, S::ROW) + u + origin;
+}
+
+// The same site for a cell that cannot reach past the domain's last row,
+// with the round's row base rb = cv ROW + origin (cv: the corner row of the
+// lane's top cell with the round's shift) and the cell's row offset voff
+// below that corner: s = (dv + voff) ROW + u + rb.
+template <int LD, int LC>
+__device__ __forceinline__ uint32_t site_rows_nowrap(uint32_t field, uint32_t cu, uint32_t rb, uint32_t voff)
+{
+    using S = RowPairShape<LD, LC>;
+    const uint32_t du = field & (S::C - 1u);
+    const uint32_t dv = (field >> LC) & (S::C - 1u);
+    return mad24(dv, S::ROW, wrap_column<LD>(du, cu)) + rb + voff * S::ROW;
 }
 
 // DB device step with each lane holding a column of CPT vertically stacked
@@ -286,7 +314,12 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
         w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
     }
     uint32_t ftop = field_of(w0, 0);  // the top cell's field of the coming round
-    uint32_t stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16), base_v0 + shy_of(f16), origin, false);
+    // the round's row base: the top cell's shifted corner row times the row
+    // stride, plus the origin (the lane's part once, the round's shift added
+    // as a uniform product)
+    const uint32_t rb0 = __umul24(base_v0, S::ROW) + origin;
+    uint32_t rb = rb0 + shy_of(f16) * S::ROW;
+    uint32_t stop = site_rows_nowrap<LD, LC>(ftop, base_u + shx_of(f16), rb, 0u);
     cpos[tid] = stop;
     if (tid < 3) flags[tid] = 0u;
     __syncthreads();
@@ -312,10 +345,11 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
             for (int j = 1; j < CPT; ++j) {
                 f[j] = field_of(w[j], k);
                 // a lane's lower cells are never in the last cell row but the bottom one
-                s[j] = site_rows<LD, LC>(f[j], cu, cv + (j << LC), origin, j == CPT - 1);
+                s[j] = j == CPT - 1 ? site_rows<LD, LC>(f[j], cu, cv + (j << LC), origin, true)
+                                    : site_rows_nowrap<LD, LC>(f[j], cu, rb, j << LC);
             }
             // the top cell's attempt of the next round, published for the column above
-            uint32_t f16n = 0u;
+            uint32_t f16n = 0u, rbn = 0u;
             if (has_next) {
                 f16n = next_block_field(A, bd, rho + 1u, tile);
                 if (k == RPB - 1) {
@@ -323,7 +357,8 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
                     w0[0] = r.x; w0[1] = r.y; w0[2] = r.z; w0[3] = r.w;
                 }
                 ftop = field_of(w0, (k + 1) % RPB);
-                stop = site_rows<LD, LC>(ftop, base_u + shx_of(f16n), base_v0 + shy_of(f16n), origin, false);
+                rbn = rb0 + shy_of(f16n) * S::ROW;
+                stop = site_rows_nowrap<LD, LC>(ftop, base_u + shx_of(f16n), rbn, 0u);
                 cpos[((rho + 1u) & 1u) * NT + tid] = stop;
             }
             // Delayed-border order dependencies (as in db_columns_round): the
@@ -388,6 +423,7 @@ __device__ __forceinline__ void sweep_db_rows(const StepArgs &A, uint32_t *smem,
                 __syncthreads();
             }
             f16 = f16n;
+            rb = rbn;
         }
     }
     copy_window_rows<false, P, S::PITCH>(A, lds, X0 >> 5, Y0 >> 2);
