@@ -793,7 +793,6 @@ int batch_run_once(okpz_batch *b, const uint64_t *n_mcs, const double *p, const 
                 fl = 0;
     }
     // square 128- or 256-site domains of 8 x 8-site cells throughout: the
-    // row-paired sweep (its own LDS size)
     // row-paired sweep (its own LDS size), two cells per lane: four per lane
     // take twice the lanes
     int ld = 0;
