@@ -1076,24 +1076,26 @@ constexpr int kMeasureThreads = 256;
 // its table entry, each later byte as its table entry (relative offsets + 8)
 // plus the previous byte's last offset broadcast to every byte, minus 8 --
 // one permute and two three-input adds per byte; no byte sum carries or
-// borrows.  Byte dot products then give sums of u and u^2 over all sites and
-// over the sites of one parity class (the class bytes of two nibbles
-// gathered into one word).  Returns q_31, the block's height change; U[k]
-// keeps the bytes of nibble k for a cross product.  MOM = false: only the
-// sum of u over all sites (what a snapshot row needs).  FIRST: the chunk
-// holding the lattice's first block, in lane 0 (the only lane that takes the
+// borrows.  Returns q_31, the block's height change; U[k] keeps the bytes of
+// nibble k for a cross product.  MOM: byte dot products give the sums of u
+// (s1e, s1o) and of u^2 (added to s2e, s2o) over the sites of each parity
+// class, each class's bytes of two nibbles gathered into one word by one
+// permute.  MOM = false: s1e = the sum of u over all sites (what a snapshot
+// row needs), the other outputs untouched.  FIRST: the chunk holding the
+// lattice's first block, in lane 0 (the only lane that takes the
 // first-block path).
 template <int R, bool MOM, bool FIRST>
-__device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, uint32_t (&U)[8], uint32_t &u2,
-                                               uint32_t &u2e, uint32_t &su, uint32_t &sue)
+__device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, uint32_t (&U)[8], uint32_t &s1e,
+                                               uint32_t &s1o, uint32_t &s2e, uint32_t &s2o)
 {
     const bool f = FIRST && (threadIdx.x & 63u) == 0u;
     // parity class "even" (x + y even): even i on even rows, odd i on odd rows;
     // bytes (m, m + 2) of nibbles k and k + 1 (permute selectors: 0-3 pick bytes
     // of the second operand, 4-7 of the first)
-    constexpr uint32_t sel = (R & 1) ? 0x07050301u : 0x06040200u;
+    constexpr uint32_t sel_e = (R & 1) ? 0x07050301u : 0x06040200u;
+    constexpr uint32_t sel_o = (R & 1) ? 0x06040200u : 0x07050301u;
     if (f) w &= ~1u;
-    uint32_t prev = 0u, s2 = 0u, s2e = 0u, s1 = 0u, s1e = 0u;
+    uint32_t prev = 0u, a1 = 0u, b1 = 0u, a2 = 0u, b2 = 0u;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const uint32_t off = ((w >> (8 * m)) & 0xFFu) << 3;  // byte offset of the table entry
@@ -1111,20 +1113,24 @@ __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, 
         prev = u1;
         U[2 * m] = u0;
         U[2 * m + 1] = u1;
-        s1 = __builtin_amdgcn_udot4(u0, 0x01010101u, s1, false);
-        s1 = __builtin_amdgcn_udot4(u1, 0x01010101u, s1, false);
         if (MOM) {
-            s2 = __builtin_amdgcn_udot4(u0, u0, s2, false);
-            s2 = __builtin_amdgcn_udot4(u1, u1, s2, false);
-            const uint32_t ev = __builtin_amdgcn_perm(u1, u0, sel);
-            s2e = __builtin_amdgcn_udot4(ev, ev, s2e, false);
-            s1e = __builtin_amdgcn_udot4(ev, 0x01010101u, s1e, false);
+            const uint32_t ev = __builtin_amdgcn_perm(u1, u0, sel_e);
+            const uint32_t od = __builtin_amdgcn_perm(u1, u0, sel_o);
+            a1 = __builtin_amdgcn_udot4(ev, 0x01010101u, a1, false);
+            b1 = __builtin_amdgcn_udot4(od, 0x01010101u, b1, false);
+            a2 = __builtin_amdgcn_udot4(ev, ev, a2, false);
+            b2 = __builtin_amdgcn_udot4(od, od, b2, false);
+        } else {
+            a1 = __builtin_amdgcn_udot4(u0, 0x01010101u, a1, false);
+            a1 = __builtin_amdgcn_udot4(u1, 0x01010101u, a1, false);
         }
     }
-    u2 += s2;
-    u2e += s2e;
-    su = s1;
-    sue = s1e;
+    s1e = a1;
+    if (MOM) {
+        s1o = b1;
+        s2e += a2;
+        s2o += b2;
+    }
     return (int32_t)(prev >> 24) - 64;  // u_31 - 64 = q_31
 }
 
@@ -1159,7 +1165,7 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
     // 16 A + sum q over its at most 4 L/64 block rows stay below 2^31
     int32_t lin_e = 0, lin_o = 0;
     int64_t quad_e = 0, quad_o = 0, xa = 0;
-    uint32_t u2 = 0, u2e = 0, ue = 0, uall = 0, us_all = 0, uts = 0;
+    uint32_t u2e = 0, u2o = 0, ue = 0, uo = 0, us_all = 0, uts = 0;
     uint32_t rows = 0;      // block rows this lane took part in
     uint32_t overlap = 0;   // at most 8 L per band
     // one chunk of 64 blocks; FIRST: the band's first chunk, whose lane 0
@@ -1186,11 +1192,14 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
         auto one_row = [&](auto rc) {
             constexpr int r = decltype(rc)::value;
             uint32_t U[8], Us[8];
-            uint32_t su = 0, sue = 0, sus = 0, suse = 0;
-            uint32_t a2 = 0, a2e = 0, b2 = 0, b2e = 0;
-            int32_t R = row_offsets<r, true, FIRST>(lut, wk[r], U, a2, a2e, su, sue);
+            uint32_t se = 0, so = 0, sus = 0, unused = 0;
+            // the u^2 sums go straight into the lane's totals when every lane
+            // holds a block, else through the row's own (added if active)
+            uint32_t t2e = 0, t2o = 0;
+            uint32_t &d2e = FULL ? u2e : t2e, &d2o = FULL ? u2o : t2o;
+            int32_t R = row_offsets<r, true, FIRST>(lut, wk[r], U, se, so, d2e, d2o);
             int32_t Rs = 0;
-            if (CROSS) Rs = row_offsets<r, false, FIRST>(lut, sk[r], Us, b2, b2e, sus, suse);
+            if (CROSS) Rs = row_offsets<r, false, FIRST>(lut, sk[r], Us, sus, unused, unused, unused);
             if (!active) R = Rs = 0;  // lanes past the end of a short band add nothing
             int32_t ex, tot, exs = 0, tot_s = 0;
             if (CROSS) {
@@ -1215,15 +1224,17 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
                 carry_s[r] += tot_s;
             }
             if (active) {
-                const int32_t sq = (int32_t)su - 2048, sqe = (int32_t)sue - 1024, sqo = sq - sqe;
+                const int32_t sqe = (int32_t)se - 1024, sqo = (int32_t)so - 1024;
                 lin_e += 16 * A + sqe;
                 lin_o += 16 * A + sqo;
                 quad_e += (int64_t)(2 * A) * (8 * A + sqe);
                 quad_o += (int64_t)(2 * A) * (8 * A + sqo);
-                u2 += a2;
-                u2e += a2e;
-                ue += sue;
-                uall += su;
+                if (!FULL) {
+                    u2e += t2e;
+                    u2o += t2o;
+                }
+                ue += se;
+                uo += so;
                 rows += 1;
                 if (CROSS) {
                     uint32_t x = 0;
@@ -1231,7 +1242,7 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
                     for (int k = 0; k < 8; ++k) x = __builtin_amdgcn_udot4(U[k], Us[k], x, false);
                     uts += x;
                     us_all += sus;
-                    xa += (int64_t)A * (32 * As + ((int32_t)sus - 2048)) + (int64_t)As * sq;
+                    xa += (int64_t)A * (32 * As + ((int32_t)sus - 2048)) + (int64_t)As * (sqe + sqo);
                 }
             }
         };
@@ -1248,12 +1259,11 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
     }
     // sums of q and q^2 from those of u = q + 64 (16 sites per class per block row)
     const int64_t n16 = 16 * (int64_t)rows;
-    const int64_t uo = (int64_t)uall - ue, u2o = (int64_t)u2 - u2e;
     int64_t s1e = lin_e, s1o = lin_o;
     int64_t s2e = quad_e + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
-    int64_t s2o = quad_o + (u2o - 128 * uo + 4096 * n16);
+    int64_t s2o = quad_o + ((int64_t)u2o - 128 * (int64_t)uo + 4096 * n16);
     int64_t sts = 0;
-    if (CROSS) sts = xa + ((int64_t)uts - 64 * ((int64_t)uall + us_all) + 4096 * 2 * n16);
+    if (CROSS) sts = xa + ((int64_t)uts - 64 * ((int64_t)ue + uo + us_all) + 4096 * 2 * n16);
     s1e = wave_sum_i64(s1e);
     s1o = wave_sum_i64(s1o);
     s2e = wave_sum_i64(s2e);
