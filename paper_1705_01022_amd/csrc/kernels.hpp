@@ -136,6 +136,16 @@ constexpr uint32_t kPatternMin = 0x9u, kPatternMax = 0x6u;
 constexpr uint32_t kFlipMin = (1u << kPatternMin) | (1u << (kPatternMin + 16u));
 constexpr uint32_t kFlipMax = (1u << kPatternMax) | (1u << (kPatternMax + 16u));
 
+// 8 (w mod 256) in one instruction (a shift of the low byte selected as the
+// operand; the compiler forms this itself for the other three bytes).
+__device__ __forceinline__ uint32_t byte0_x8(uint32_t w)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(3u), "v"(w));
+    return r;
+}
+
 // a + b + c in one instruction; c uniform.
 __device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -1098,7 +1108,8 @@ __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, 
     uint32_t prev = 0u, a1 = 0u, b1 = 0u, a2 = 0u, b2 = 0u;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const uint32_t off = ((w >> (8 * m)) & 0xFFu) << 3;  // byte offset of the table entry
+        // byte offset of the table entry
+        const uint32_t off = m == 0 ? byte0_x8(w) : ((w >> (8 * m)) & 0xFFu) << 3;
         const uint2 e = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lut) + (m ? 2048u : 0u) + off);
         uint32_t u0, u1;
         if (m == 0) {
@@ -1164,7 +1175,9 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
     // |h| <= L on the periodic surface (gauge h(0,0) = 0), so a lane's sums of
     // 16 A + sum q over its at most 4 L/64 block rows stay below 2^31
     int32_t lin_e = 0, lin_o = 0;
-    int64_t quad_e = 0, quad_o = 0, xa = 0;
+    // per class, sum h^2 = 16 A^2 + 2 A sum q + sum q^2 over a block row: the
+    // A-terms summed over rows as sum A^2 and sum A sum q_class
+    int64_t aa = 0, aq_e = 0, aq_o = 0, xa = 0;
     uint32_t u2e = 0, u2o = 0, ue = 0, uo = 0, us_all = 0, uts = 0;
     uint32_t rows = 0;      // block rows this lane took part in
     uint32_t overlap = 0;   // at most 8 L per band
@@ -1227,8 +1240,9 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
                 const int32_t sqe = (int32_t)se - 1024, sqo = (int32_t)so - 1024;
                 lin_e += 16 * A + sqe;
                 lin_o += 16 * A + sqo;
-                quad_e += (int64_t)(2 * A) * (8 * A + sqe);
-                quad_o += (int64_t)(2 * A) * (8 * A + sqo);
+                aa += (int64_t)A * A;
+                aq_e += (int64_t)A * sqe;
+                aq_o += (int64_t)A * sqo;
                 if (!FULL) {
                     u2e += t2e;
                     u2o += t2o;
@@ -1260,8 +1274,8 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
     // sums of q and q^2 from those of u = q + 64 (16 sites per class per block row)
     const int64_t n16 = 16 * (int64_t)rows;
     int64_t s1e = lin_e, s1o = lin_o;
-    int64_t s2e = quad_e + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
-    int64_t s2o = quad_o + ((int64_t)u2o - 128 * (int64_t)uo + 4096 * n16);
+    int64_t s2e = 16 * aa + 2 * aq_e + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
+    int64_t s2o = 16 * aa + 2 * aq_o + ((int64_t)u2o - 128 * (int64_t)uo + 4096 * n16);
     int64_t sts = 0;
     if (CROSS) sts = xa + ((int64_t)uts - 64 * ((int64_t)ue + uo + us_all) + 4096 * 2 * n16);
     s1e = wave_sum_i64(s1e);
