@@ -1172,12 +1172,13 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
         h0r[r] = h0[4 * band + r];
         if (CROSS) h0sr[r] = h0s[4 * band + r];
     }
-    // |h| <= L on the periodic surface (gauge h(0,0) = 0), so a lane's sums of
-    // 16 A + sum q over its at most 4 L/64 block rows stay below 2^31
-    int32_t lin_e = 0, lin_o = 0;
-    // per class, sum h^2 = 16 A^2 + 2 A sum q + sum q^2 over a block row: the
-    // A-terms summed over rows as sum A^2 and sum A sum q_class
-    int64_t aa = 0, aq_e = 0, aq_o = 0, xa = 0;
+    // per class and block row, sum h = 16 A + sum q and sum h^2 = 16 A^2 +
+    // 2 A sum q + sum q^2: the A-terms summed over the lane's rows as sum A,
+    // sum A^2 and sum A sum u_class (q = u - 64).  |A| <= L <= 2^17 on the
+    // periodic surface (gauge h(0,0) = 0) and a lane has at most 4 L/2048
+    // block rows of a band, so sum A stays below 2^25
+    int32_t sa = 0;
+    int64_t aa = 0, au_e = 0, au_o = 0, xa = 0;
     uint32_t u2e = 0, u2o = 0, ue = 0, uo = 0, us_all = 0, uts = 0;
     uint32_t rows = 0;      // block rows this lane took part in
     uint32_t overlap = 0;   // at most 8 L per band
@@ -1237,12 +1238,10 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
                 carry_s[r] += tot_s;
             }
             if (active) {
-                const int32_t sqe = (int32_t)se - 1024, sqo = (int32_t)so - 1024;
-                lin_e += 16 * A + sqe;
-                lin_o += 16 * A + sqo;
+                sa += A;
                 aa += (int64_t)A * A;
-                aq_e += (int64_t)A * sqe;
-                aq_o += (int64_t)A * sqo;
+                au_e += (int64_t)A * (int32_t)se;
+                au_o += (int64_t)A * (int32_t)so;
                 if (!FULL) {
                     u2e += t2e;
                     u2o += t2o;
@@ -1251,12 +1250,13 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
                 uo += so;
                 rows += 1;
                 if (CROSS) {
-                    uint32_t x = 0;
+                    // sum u_t u_s, chained straight into the lane's total
+                    uint32_t x = uts;
 #pragma unroll
                     for (int k = 0; k < 8; ++k) x = __builtin_amdgcn_udot4(U[k], Us[k], x, false);
-                    uts += x;
+                    uts = x;
                     us_all += sus;
-                    xa += (int64_t)A * (32 * As + ((int32_t)sus - 2048)) + (int64_t)As * (sqe + sqo);
+                    xa += (int64_t)A * (32 * As + ((int32_t)sus - 2048)) + (int64_t)As * ((int32_t)(se + so) - 2048);
                 }
             }
         };
@@ -1273,9 +1273,10 @@ __device__ __forceinline__ void rows_band(const uint32_t *lut, const uint32_t *_
     }
     // sums of q and q^2 from those of u = q + 64 (16 sites per class per block row)
     const int64_t n16 = 16 * (int64_t)rows;
-    int64_t s1e = lin_e, s1o = lin_o;
-    int64_t s2e = 16 * aa + 2 * aq_e + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
-    int64_t s2o = 16 * aa + 2 * aq_o + ((int64_t)u2o - 128 * (int64_t)uo + 4096 * n16);
+    int64_t s1e = 16 * (int64_t)sa + (int64_t)ue - 64 * n16;
+    int64_t s1o = 16 * (int64_t)sa + (int64_t)uo - 64 * n16;
+    int64_t s2e = 16 * aa + 2 * (au_e - 1024 * (int64_t)sa) + ((int64_t)u2e - 128 * (int64_t)ue + 4096 * n16);
+    int64_t s2o = 16 * aa + 2 * (au_o - 1024 * (int64_t)sa) + ((int64_t)u2o - 128 * (int64_t)uo + 4096 * n16);
     int64_t sts = 0;
     if (CROSS) sts = xa + ((int64_t)uts - 64 * ((int64_t)ue + uo + us_all) + 4096 * 2 * n16);
     s1e = wave_sum_i64(s1e);
