@@ -1105,7 +1105,8 @@ __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, 
     constexpr uint32_t sel_e = (R & 1) ? 0x07050301u : 0x06040200u;
     constexpr uint32_t sel_o = (R & 1) ? 0x06040200u : 0x07050301u;
     if (f) w &= ~1u;
-    uint32_t prev = 0u, a1 = 0u, b1 = 0u, a2 = 0u, b2 = 0u;
+    // the u^2 chains continue the caller's sums
+    uint32_t prev = 0u, a1 = 0u, b1 = 0u, a2 = s2e, b2 = s2o;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         // byte offset of the table entry
@@ -1139,8 +1140,8 @@ __device__ __forceinline__ int32_t row_offsets(const uint32_t *lut, uint32_t w, 
     s1e = a1;
     if (MOM) {
         s1o = b1;
-        s2e += a2;
-        s2o += b2;
+        s2e = a2;
+        s2o = b2;
     }
     return (int32_t)(prev >> 24) - 64;  // u_31 - 64 = q_31
 }
