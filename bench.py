@@ -43,14 +43,14 @@ VALU_PEAK_GOPS = CUS * SIMDS_PER_CU * 16 * CLOCK_GHZ
 DEVICE_SOURCES = ("paper_1705_01022_amd/csrc/kernels.hpp", "paper_1705_01022_amd/csrc/db_rows.hpp",
                   "paper_1705_01022_amd/csrc/okpz.hip", "paper_1705_01022_amd/csrc/philox.hpp",
                   "paper_1705_01022_amd/csrc/internal.hpp")
-MEASURED = {"sources": "c350a8084f308743", "workload": "L131072",
+MEASURED = {"sources": "db81be07e6f37fc1", "workload": "L131072",
             # per launch of step_db_rows_kernel<true, 4, 8, 3>, averages of 12 dispatches
-            "FETCH_SIZE_KiB": 922819.0, "WRITE_SIZE_KiB": 1584204.0,
+            "FETCH_SIZE_KiB": 922611.0, "WRITE_SIZE_KiB": 1584208.0,
             "SQ_INSTS_VALU": 2.69274e9, "SQ_ACTIVE_INST_VALU": 2.69274e9, "SQ_INSTS_SALU": 1.87680e9,
             "SQ_INSTS_LDS": 5.85401e8, "SQ_LDS_IDX_ACTIVE": 2.47391e9, "SQ_LDS_BANK_CONFLICT": 8.60797e8,
-            "SQ_WAIT_INST_LDS": 3.21224e9,
+            "SQ_WAIT_INST_LDS": 3.21385e9,
             # GRBM_GUI_ACTIVE summed over the 8 XCDs, divided by 8: the dispatch's GPU cycles
-            "GRBM_GUI_ACTIVE": 107582000.0 / 8, "launch_ms": 5.6817}
+            "GRBM_GUI_ACTIVE": 108021000.0 / 8, "launch_ms": 5.7300}
 
 
 def device_sources_hash() -> str:
